@@ -1,0 +1,576 @@
+/*
+ * Plain FP64 CPU oracle for the Hermite-regularized lattice Boltzmann step
+ * (Brogi, Malaspinas, Chopard & Bonadonna, "Hermite regularization of the
+ * Lattice Boltzmann Method for open source computational aeroacoustics",
+ * arXiv:1710.02065).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference that the
+ * GPU library is checked against.  It shares no code, header, table or
+ * constant generator with the HIP path; only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg load it.  It is written to be read
+ * against the paper, not to be fast: every cell is handled one at a time,
+ * with the full 3x3 and 3x3x3 moment tensors, in the order the paper states
+ * the algorithm.  OpenMP over the outermost axis is the only concession to
+ * speed; the update has no reductions, so results do not depend on threads.
+ *
+ * Readings of passages the paper leaves open (all listed in the design notes):
+ *  - eq. (eqH): the first-order term is xi.u/cs^2 (the printed form lacks
+ *    ".u"); third-order equilibrium coefficients are rho*u*u*u from
+ *    eq. (recursive1).
+ *  - eq. (neqH): no rho factor; a2_neq is an absolute moment.
+ *  - a2 = Pi - rho*cs^2*I (the printed "a2 = P - rho(uu - delta)" is garbled);
+ *    a2_neq = Pi - rho*cs^2*I - rho*u*u.
+ *  - third-order basis per lattice (Sec. II.A, "special property" of D2Q9 and
+ *    D3Q27): D2Q9 {xxy, xyy}; D3Q27 {xxy, xyy, xxz, xzz, yyz, yzz, xyz};
+ *    D3Q19 (not covered by that property) uses the lattice-orthogonal
+ *    combinations (H_xxy +- H_yzz) and likewise for the x- and z-odd pairs.
+ *    Each basis element k is rebuilt as w_i H_k,i c_k / N_k, with N_k the
+ *    lattice norm sum_i w_i H_k,i^2, so the rebuilt populations carry the
+ *    target third-order moment c_k exactly.
+ *  - sponge (Sec. II.C, eqs. spongeLB, dampingLBM, modifiedMoments): the
+ *    unspecified factors n and m are 1/2, which makes the homogeneous decay
+ *    rate of the BGK variant equal the effective damping sigma_eff the
+ *    paper prints (eq. effectiveCoefficient).  rho* and j* are solved in
+ *    closed form.  The force is added in full.
+ *  - pull streaming of post-collision populations; halfway bounce-back
+ *    (wall at rest); specular free-slip; zero-gradient outflow by clamping
+ *    the source to the last interior row; equilibrium inlet cells.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_CS2 (1.0 / 3.0)
+
+/* ------------------------------------------------------------------------ */
+/* Lattices (Sec. II.A: D2Q9, D3Q19, D3Q27 Gauss-Hermite quadratures).       */
+/* The paper cites the lattices without printing tables; these are the       */
+/* textbook velocity sets and weights, in the direction order documented in  */
+/* the library header: rest, then opposite pairs (odd i, i+1).               */
+/* ------------------------------------------------------------------------ */
+
+static const int ORA_D2Q9_XI[9][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+static const double ORA_D2Q9_W[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,
+                                     1.0 / 9,  1.0 / 9,  1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+static const int ORA_D3Q27_XI[27][3] = {
+    {0, 0, 0},                                                 /* rest   */
+    {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},         /* faces  */
+    {0, 0, 1},   {0, 0, -1},                                   /*        */
+    {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},         /* edges  */
+    {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},         /*        */
+    {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},         /*        */
+    {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},        /* corners*/
+    {1, -1, 1},  {-1, 1, -1}, {-1, 1, 1},  {1, -1, -1}};
+
+typedef struct {
+  int q, d;
+  int xi[27][3];
+  double w[27];
+  int opp[27];
+} ora_lattice;
+
+/* Fill *L for lattice id 9, 19 or 27; returns 0, or -1 for an unknown id. */
+static int ora_make_lattice(int id, ora_lattice* L) {
+  int i, a;
+  memset(L, 0, sizeof(*L));
+  if (id == 9) {
+    L->q = 9;
+    L->d = 2;
+    for (i = 0; i < 9; ++i) {
+      for (a = 0; a < 3; ++a) L->xi[i][a] = ORA_D2Q9_XI[i][a];
+      L->w[i] = ORA_D2Q9_W[i];
+    }
+  } else if (id == 19 || id == 27) {
+    L->q = id;
+    L->d = 3;
+    for (i = 0; i < id; ++i) {
+      int n2 = 0;
+      for (a = 0; a < 3; ++a) {
+        L->xi[i][a] = ORA_D3Q27_XI[i][a];
+        n2 += ORA_D3Q27_XI[i][a] * ORA_D3Q27_XI[i][a];
+      }
+      if (id == 19) /* D3Q19: 1/3 rest, 1/18 faces, 1/36 edges */
+        L->w[i] = n2 == 0 ? 1.0 / 3 : (n2 == 1 ? 1.0 / 18 : 1.0 / 36);
+      else /* D3Q27: 8/27, 2/27, 1/54, 1/216 */
+        L->w[i] = n2 == 0 ? 8.0 / 27
+                          : (n2 == 1 ? 2.0 / 27 : (n2 == 2 ? 1.0 / 54 : 1.0 / 216));
+    }
+  } else {
+    return -1;
+  }
+  for (i = 0; i < L->q; ++i) {
+    int j;
+    for (j = 0; j < L->q; ++j)
+      if (L->xi[j][0] == -L->xi[i][0] && L->xi[j][1] == -L->xi[i][1] &&
+          L->xi[j][2] == -L->xi[i][2])
+        L->opp[i] = j;
+  }
+  return 0;
+}
+
+int ora_lattice_info(int id, int* q, int* d, int* xi, double* w, int* opp) {
+  ora_lattice L;
+  int i, a;
+  if (ora_make_lattice(id, &L)) return -1;
+  if (q) *q = L.q;
+  if (d) *d = L.d;
+  for (i = 0; i < L.q; ++i) {
+    if (xi)
+      for (a = 0; a < 3; ++a) xi[3 * i + a] = L.xi[i][a];
+    if (w) w[i] = L.w[i];
+    if (opp) opp[i] = L.opp[i];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hermite polynomials on the lattice (eq. HE with the lattice weights).     */
+/* ------------------------------------------------------------------------ */
+
+/* Second-order Hermite polynomial H_ab(xi_i) = xi_a xi_b - cs^2 delta_ab. */
+static double ora_h2(const ora_lattice* L, int i, int a, int b) {
+  return (double)L->xi[i][a] * L->xi[i][b] - (a == b ? ORA_CS2 : 0.0);
+}
+
+/* Third-order Hermite polynomial
+ * H_abc = xi_a xi_b xi_c - cs^2 (xi_a d_bc + xi_b d_ac + xi_c d_ab). */
+static double ora_h3(const ora_lattice* L, int i, int a, int b, int c) {
+  double xa = L->xi[i][a], xb = L->xi[i][b], xc = L->xi[i][c];
+  return xa * xb * xc -
+         ORA_CS2 * (xa * (b == c) + xb * (a == c) + xc * (a == b));
+}
+
+/* Third-order part of a regularized population:
+ *   sum_k H_k,i c_k / N_k
+ * over the basis the lattice supports (see header comment), with c_k the
+ * matching combination of the symmetric 3rd-order tensor a3 and N_k the
+ * lattice norm of H_k, both in closed form. */
+static double ora_third_order(const ora_lattice* L, int i, double a3[3][3][3]) {
+  const double cs6 = ORA_CS2 * ORA_CS2 * ORA_CS2;
+  enum { X = 0, Y = 1, Z = 2 };
+  if (L->q == 9) {
+    return (ora_h3(L, i, X, X, Y) * a3[X][X][Y] +
+            ora_h3(L, i, X, Y, Y) * a3[X][Y][Y]) /
+           (2 * cs6);
+  }
+  if (L->q == 27) {
+    double s = ora_h3(L, i, X, X, Y) * a3[X][X][Y] +
+               ora_h3(L, i, X, Y, Y) * a3[X][Y][Y] +
+               ora_h3(L, i, X, X, Z) * a3[X][X][Z] +
+               ora_h3(L, i, X, Z, Z) * a3[X][Z][Z] +
+               ora_h3(L, i, Y, Y, Z) * a3[Y][Y][Z] +
+               ora_h3(L, i, Y, Z, Z) * a3[Y][Z][Z];
+    return s / (2 * cs6) + ora_h3(L, i, X, Y, Z) * a3[X][Y][Z] / cs6;
+  }
+  /* D3Q19: for each odd axis the pair (P, Q) of third-order polynomials that
+   * the lattice does not separate is replaced by (P + Q) with norm 2 cs^6 and
+   * (P - Q) with norm 6 cs^6; coefficients a_P +- a_Q. */
+  {
+    double s = 0.0;
+    /* pairs: (xxy, yzz) odd in y, (xyy, xzz) odd in x, (xxz, yyz) odd in z */
+    const int pairs[3][2][3] = {{{X, X, Y}, {Y, Z, Z}},
+                                {{X, Y, Y}, {X, Z, Z}},
+                                {{X, X, Z}, {Y, Y, Z}}};
+    int p;
+    for (p = 0; p < 3; ++p) {
+      const int* P = pairs[p][0];
+      const int* Q = pairs[p][1];
+      double hp = ora_h3(L, i, P[0], P[1], P[2]);
+      double hq = ora_h3(L, i, Q[0], Q[1], Q[2]);
+      double ap = a3[P[0]][P[1]][P[2]];
+      double aq = a3[Q[0]][Q[1]][Q[2]];
+      s += (hp + hq) * (ap + aq) / (2 * cs6) + (hp - hq) * (ap - aq) / (6 * cs6);
+    }
+    return s;
+  }
+}
+
+/* Extended equilibrium f^{eqH}_i(rho, u) of eq. (eqH): the second-order
+ * polynomial of eq. (truncatedEq) plus the third-order Hermite terms with the
+ * equilibrium coefficients a3_eq = rho u u u of eq. (recursive1). */
+static void ora_feq(const ora_lattice* L, double rho, const double u[3],
+                    double* feq) {
+  const double cs2 = ORA_CS2, cs4 = ORA_CS2 * ORA_CS2;
+  double a3[3][3][3];
+  int i, a, b, c;
+  for (a = 0; a < 3; ++a)
+    for (b = 0; b < 3; ++b)
+      for (c = 0; c < 3; ++c) a3[a][b][c] = rho * u[a] * u[b] * u[c];
+  for (i = 0; i < L->q; ++i) {
+    double xu = 0.0, h2uu = 0.0;
+    for (a = 0; a < L->d; ++a) xu += L->xi[i][a] * u[a];
+    for (a = 0; a < L->d; ++a)
+      for (b = 0; b < L->d; ++b) h2uu += ora_h2(L, i, a, b) * u[a] * u[b];
+    feq[i] = L->w[i] * (rho * (1.0 + xu / cs2 + h2uu / (2 * cs4)) +
+                        ora_third_order(L, i, a3));
+  }
+}
+
+/* Regularized non-equilibrium f^{neqH}_i of eq. (neqH): the second-order
+ * term from a2_neq plus the third-order term whose coefficients come from the
+ * recursion eq. (recursive2) at n = 3:
+ *   a3_neq,abc = u_a a2_bc + u_b a2_ac + u_c a2_ab. */
+static void ora_fneq(const ora_lattice* L, const double u[3],
+                     double a2[3][3], double* fneq) {
+  const double cs4 = ORA_CS2 * ORA_CS2;
+  double a3[3][3][3];
+  int i, a, b, c;
+  for (a = 0; a < 3; ++a)
+    for (b = 0; b < 3; ++b)
+      for (c = 0; c < 3; ++c)
+        a3[a][b][c] = u[a] * a2[b][c] + u[b] * a2[a][c] + u[c] * a2[a][b];
+  for (i = 0; i < L->q; ++i) {
+    double h2a2 = 0.0;
+    for (a = 0; a < L->d; ++a)
+      for (b = 0; b < L->d; ++b) h2a2 += ora_h2(L, i, a, b) * a2[a][b];
+    fneq[i] = L->w[i] * (h2a2 / (2 * cs4) + ora_third_order(L, i, a3));
+  }
+}
+
+/* a2 in the packed order (xx, yy, zz, xy, xz, yz) -> full symmetric tensor */
+static void ora_unpack6(const double* p, double t[3][3]) {
+  t[0][0] = p[0];
+  t[1][1] = p[1];
+  t[2][2] = p[2];
+  t[0][1] = t[1][0] = p[3];
+  t[0][2] = t[2][0] = p[4];
+  t[1][2] = t[2][1] = p[5];
+}
+
+void ora_equilibrium(int lattice, double rho, const double* u, double* feq) {
+  ora_lattice L;
+  if (ora_make_lattice(lattice, &L)) return;
+  ora_feq(&L, rho, u, feq);
+}
+
+void ora_noneq(int lattice, const double* u, const double* a2packed,
+               double* fneq) {
+  ora_lattice L;
+  double a2[3][3];
+  if (ora_make_lattice(lattice, &L)) return;
+  ora_unpack6(a2packed, a2);
+  ora_fneq(&L, u, a2, fneq);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-cell collision: eq. (optimizedLB), with the damping force of          */
+/* eqs. (spongeLB) and (dampingLBM) when chi > 0.                            */
+/* f holds the pre-collision (streamed) populations; post receives the       */
+/* populations to stream.  rho_star/u_star (may be NULL) receive the         */
+/* moments used in the rebuild.                                              */
+/* ------------------------------------------------------------------------ */
+static void ora_collide_cell(const ora_lattice* L, const double* f, double tau,
+                             double chi, double rho_ref, const double* u_ref,
+                             double* post, double* rho_star, double* u_star) {
+  const double cs2 = ORA_CS2;
+  double rho = 0.0, j[3] = {0, 0, 0}, Pi[3][3] = {{0}};
+  double rs, js[3], u[3], a2[3][3];
+  double E[27], N[27], Eref[27];
+  int i, a, b;
+
+  /* eq. (moments) and the second-order moment Pi = sum f xi xi */
+  for (i = 0; i < L->q; ++i) {
+    rho += f[i];
+    for (a = 0; a < 3; ++a) {
+      j[a] += f[i] * L->xi[i][a];
+      for (b = 0; b < 3; ++b) Pi[a][b] += f[i] * L->xi[i][a] * L->xi[i][b];
+    }
+  }
+  /* eq. (modifiedMoments) with n = m = 1/2: rho* = rho + sum F / 2 and
+   * rho* u* = j + sum F xi / 2, where sum F = chi (rho_ref - rho*) and
+   * sum F xi = chi (rho_ref u_ref - rho* u*); solved for rho*, rho* u*.
+   * With chi = 0 these are the plain moments of eq. (moments). */
+  rs = (rho + 0.5 * chi * rho_ref) / (1.0 + 0.5 * chi);
+  for (a = 0; a < 3; ++a)
+    js[a] = (j[a] + 0.5 * chi * rho_ref * u_ref[a]) / (1.0 + 0.5 * chi);
+  for (a = 0; a < 3; ++a) u[a] = js[a] / rs;
+
+  /* non-equilibrium second-order Hermite coefficient (in the lattice's d
+   * dimensions; the z row and column stay zero in 2D) */
+  for (a = 0; a < 3; ++a)
+    for (b = 0; b < 3; ++b)
+      a2[a][b] = (a < L->d && b < L->d)
+                     ? Pi[a][b] - rs * cs2 * (a == b) - rs * u[a] * u[b]
+                     : 0.0;
+
+  ora_feq(L, rs, u, E);
+  ora_fneq(L, u, a2, N);
+  if (chi != 0.0) ora_feq(L, rho_ref, u_ref, Eref);
+  for (i = 0; i < L->q; ++i) {
+    post[i] = E[i] + (1.0 - 1.0 / tau) * N[i];
+    if (chi != 0.0) post[i] += chi * (Eref[i] - E[i]);
+  }
+  if (rho_star) *rho_star = rs;
+  if (u_star)
+    for (a = 0; a < 3; ++a) u_star[a] = u[a];
+}
+
+void ora_collide(int lattice, const double* f, double tau, double chi,
+                 double rho_ref, const double* u_ref, double* post) {
+  ora_lattice L;
+  if (ora_make_lattice(lattice, &L)) return;
+  ora_collide_cell(&L, f, tau, chi, rho_ref, u_ref, post, NULL, NULL);
+}
+
+/* Standard LBM-BGK collision, eq. (standardLB) with the second-order
+ * equilibrium of eq. (truncatedEq), plus the same damping force and
+ * modified moments as above.  Test mode only: it is the operator the paper's
+ * 1D sponge analysis (eq. effectiveCoefficient) is stated for. */
+void ora_collide_bgk(int lattice, const double* f, double tau, double chi,
+                     double rho_ref, const double* u_ref, double* post) {
+  ora_lattice L;
+  const double cs2 = ORA_CS2, cs4 = ORA_CS2 * ORA_CS2;
+  double rho = 0.0, j[3] = {0, 0, 0}, rs, u[3], uref_[3];
+  int i, a;
+  if (ora_make_lattice(lattice, &L)) return;
+  for (i = 0; i < L.q; ++i) {
+    rho += f[i];
+    for (a = 0; a < 3; ++a) j[a] += f[i] * L.xi[i][a];
+  }
+  rs = (rho + 0.5 * chi * rho_ref) / (1.0 + 0.5 * chi);
+  for (a = 0; a < 3; ++a) {
+    u[a] = (j[a] + 0.5 * chi * rho_ref * u_ref[a]) / (1.0 + 0.5 * chi) / rs;
+    uref_[a] = u_ref[a];
+  }
+  for (i = 0; i < L.q; ++i) {
+    double xu = 0, uu = 0, xr = 0, rr = 0, feq, fref;
+    for (a = 0; a < 3; ++a) {
+      xu += L.xi[i][a] * u[a];
+      uu += u[a] * u[a];
+      xr += L.xi[i][a] * uref_[a];
+      rr += uref_[a] * uref_[a];
+    }
+    feq = L.w[i] * rs * (1 + xu / cs2 + xu * xu / (2 * cs4) - uu / (2 * cs2));
+    fref = L.w[i] * rho_ref *
+           (1 + xr / cs2 + xr * xr / (2 * cs4) - rr / (2 * cs2));
+    post[i] = f[i] - (f[i] - feq) / tau + chi * (fref - feq);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the k-th output (k >= 0) of */
+/* the generator seeded with `seed`.  Used for the inlet perturbation.       */
+/* ------------------------------------------------------------------------ */
+uint64_t ora_splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* uniform in [-1, 1) with 2^-23 spacing from the top 24 bits */
+static double ora_uniform_pm1(uint64_t z) {
+  return (double)(z >> 40) * (1.0 / 8388608.0) - 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid update                                                               */
+/* ------------------------------------------------------------------------ */
+
+enum { ORA_PERIODIC = 0, ORA_FREESLIP = 1, ORA_OUTFLOW = 2 };
+enum { ORA_FLUID = 0, ORA_SOLID = 1, ORA_INLET = 2 };
+
+typedef struct {
+  int lattice;              /* 9, 19, 27 */
+  int level;                /* refinement level of this grid (0 = coarse) */
+  int64_t nx, ny, nz;       /* nz = 1 in 2D */
+  double tau, rho0;
+  double u_in[3];           /* inlet velocity U * u_dir */
+  int face_bc[6];           /* x-, x+, y-, y+, z-, z+ */
+  int sponge_width[6];      /* cells, per face; 0 = none */
+  double chi_max, rho_ref, u_ref[3];
+  uint64_t seed;
+  double inlet_noise;
+} ora_grid;
+
+/* Sponge strength chi(x) = chi_max * max over faces of the polynomial
+ * profile sigma of Sec. II.C,
+ *   sigma(s) = 3125 (L - s)(s - s0)^4 / (256 (L - s0)^5),
+ * with s the coordinate normal to the face, s0 = n - W the inner edge and
+ * L = n one past the last node, for a face of width W on an axis of n nodes;
+ * the low face uses the mirrored coordinate n - 1 - x. */
+double ora_sponge_chi(const ora_grid* g, int64_t x, int64_t y, int64_t z) {
+  int64_t pos[3] = {x, y, z}, dims[3] = {g->nx, g->ny, g->nz};
+  double best = 0.0;
+  int face;
+  if (g->chi_max == 0.0) return 0.0;
+  for (face = 0; face < 6; ++face) {
+    int axis = face / 2;
+    int64_t n = dims[axis], W = g->sponge_width[face];
+    double s, s0, Lend, sig;
+    if (W <= 0) continue;
+    s = (face % 2 == 1) ? (double)pos[axis] : (double)(n - 1 - pos[axis]);
+    s0 = (double)(n - W);
+    Lend = (double)n;
+    if (s < s0) continue;
+    sig = 3125.0 * (Lend - s) * pow(s - s0, 4) / (256.0 * pow(Lend - s0, 5));
+    if (sig > best) best = sig;
+  }
+  return g->chi_max * best;
+}
+
+static int64_t ora_cell(const ora_grid* g, int64_t x, int64_t y, int64_t z) {
+  return (z * g->ny + y) * g->nx + x;
+}
+
+/* Direction index with the component on `axis` reversed (specular mirror). */
+static int ora_mirror(const ora_lattice* L, int i, int axis) {
+  int j, a;
+  for (j = 0; j < L->q; ++j) {
+    int same = 1;
+    for (a = 0; a < 3; ++a) {
+      int want = (a == axis) ? -L->xi[i][a] : L->xi[i][a];
+      if (L->xi[j][a] != want) same = 0;
+    }
+    if (same) return j;
+  }
+  return -1;
+}
+
+/* Pre-collision population i at cell (x, y, z), pulled from the
+ * post-collision field fin (left side of eq. optimizedLB read backwards):
+ * the source is x - xi_i, mapped through the face rules axis by axis, and a
+ * link whose source is a SOLID cell is bounced back halfway. */
+static double ora_pull(const ora_grid* g, const ora_lattice* L,
+                       const uint8_t* mask, const double* fin, int64_t x,
+                       int64_t y, int64_t z, int i) {
+  int64_t N = g->nx * g->ny * g->nz;
+  int64_t s[3] = {x - L->xi[i][0], y - L->xi[i][1], z - L->xi[i][2]};
+  int64_t dims[3] = {g->nx, g->ny, g->nz};
+  int si = i, a;
+  for (a = 0; a < L->d; ++a) {
+    int64_t n = dims[a];
+    int face;
+    if (s[a] >= 0 && s[a] < n) continue;
+    face = 2 * a + (s[a] >= n ? 1 : 0);
+    switch (g->face_bc[face]) {
+      case ORA_PERIODIC:
+        s[a] = (s[a] % n + n) % n;
+        break;
+      case ORA_FREESLIP: /* the particle was reflected at the wall */
+        s[a] = s[a] < 0 ? 0 : n - 1;
+        si = ora_mirror(L, si, a);
+        break;
+      default: /* ORA_OUTFLOW: zero gradient, copy of the last row */
+        s[a] = s[a] < 0 ? 0 : n - 1;
+        break;
+    }
+  }
+  if (mask && mask[ora_cell(g, s[0], s[1], s[2])] == ORA_SOLID)
+    return fin[(int64_t)L->opp[i] * N + ora_cell(g, x, y, z)];
+  return fin[(int64_t)si * N + ora_cell(g, s[0], s[1], s[2])];
+}
+
+/* Inlet velocity at a cell for the state being produced at time index t:
+ * u_in * (1 + noise * r), r uniform in [-1, 1) per component, drawn from
+ * SplitMix64 with counter ((t * 2 + level) * N + cell) * 3 + component. */
+static void ora_inlet_velocity(const ora_grid* g, int64_t cell, int64_t t,
+                               double* u) {
+  int64_t N = g->nx * g->ny * g->nz;
+  int a;
+  for (a = 0; a < 3; ++a) {
+    uint64_t k = (((uint64_t)t * 2u + (uint64_t)g->level) * (uint64_t)N +
+                  (uint64_t)cell) * 3u + (uint64_t)a;
+    double r = ora_uniform_pm1(ora_splitmix64(g->seed, k));
+    u[a] = g->u_in[a] * (1.0 + g->inlet_noise * r);
+  }
+}
+
+/* Initial post-collision state (the state streamed at t = 0):
+ * f = f^{eqH}(rho, u) + (1 - 1/tau) f^{neqH}(a2_neq, u).
+ * rho [N], u [3][N] (z ignored in 2D), pineq [6][N] (xx,yy,zz,xy,xz,yz);
+ * a NULL field means rho0, the inlet velocity or zero. */
+void ora_init(const ora_grid* g, const double* rho, const double* u,
+              const double* pineq, double* f) {
+  ora_lattice L;
+  int64_t N = g->nx * g->ny * g->nz, c;
+  if (ora_make_lattice(g->lattice, &L)) return;
+#pragma omp parallel for schedule(static)
+  for (c = 0; c < N; ++c) {
+    double r = rho ? rho[c] : g->rho0, uu[3], p6[6] = {0, 0, 0, 0, 0, 0};
+    double a2[3][3], E[27], Nq[27];
+    int a, i;
+    for (a = 0; a < 3; ++a) uu[a] = u ? u[(int64_t)a * N + c] : g->u_in[a];
+    if (L.d == 2) uu[2] = 0.0;
+    if (pineq)
+      for (a = 0; a < 6; ++a) p6[a] = pineq[(int64_t)a * N + c];
+    if (L.d == 2) p6[2] = p6[4] = p6[5] = 0.0;
+    ora_unpack6(p6, a2);
+    ora_feq(&L, r, uu, E);
+    ora_fneq(&L, uu, a2, Nq);
+    for (i = 0; i < L.q; ++i)
+      f[(int64_t)i * N + c] = E[i] + (1.0 - 1.0 / g->tau) * Nq[i];
+  }
+}
+
+/* Full update of the post-collision field from time t_new - 1 to t_new.
+ * mask may be NULL (all fluid).  SOLID cells are copied unchanged. */
+void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
+              double* fout, int64_t t_new) {
+  ora_lattice L;
+  int64_t N = g->nx * g->ny * g->nz, row;
+  if (ora_make_lattice(g->lattice, &L)) return;
+#pragma omp parallel for schedule(static)
+  for (row = 0; row < g->ny * g->nz; ++row) {
+    int64_t y = row % g->ny, z = row / g->ny, x;
+    for (x = 0; x < g->nx; ++x) {
+        int64_t c = ora_cell(g, x, y, z);
+        uint8_t m = mask ? mask[c] : ORA_FLUID;
+        double f[27], post[27];
+        int i;
+        if (m == ORA_SOLID) {
+          for (i = 0; i < L.q; ++i)
+            fout[(int64_t)i * N + c] = fin[(int64_t)i * N + c];
+          continue;
+        }
+        if (m == ORA_INLET) {
+          double uin[3];
+          ora_inlet_velocity(g, c, t_new, uin);
+          if (L.d == 2) uin[2] = 0.0;
+          ora_feq(&L, g->rho0, uin, post);
+        } else {
+          double chi = ora_sponge_chi(g, x, y, z);
+          for (i = 0; i < L.q; ++i)
+            f[i] = ora_pull(g, &L, mask, fin, x, y, z, i);
+          ora_collide_cell(&L, f, g->tau, chi, g->rho_ref, g->u_ref, post,
+                           NULL, NULL);
+        }
+        for (i = 0; i < L.q; ++i) fout[(int64_t)i * N + c] = post[i];
+    }
+  }
+}
+
+/* Density and velocity of the stored post-collision state at each cell:
+ * rho = sum f, u = sum f xi / rho (eq. moments).  In cells without damping
+ * the collision conserves both, so these equal the pre-collision moments of
+ * the same time level.  SOLID cells report zero. */
+void ora_moments(const ora_grid* g, const uint8_t* mask, const double* f,
+                 double* rho_out, double* u_out) {
+  ora_lattice L;
+  int64_t N = g->nx * g->ny * g->nz, c;
+  if (ora_make_lattice(g->lattice, &L)) return;
+#pragma omp parallel for schedule(static)
+  for (c = 0; c < N; ++c) {
+    double r = 0, j[3] = {0, 0, 0};
+    int i, a;
+    if (mask && mask[c] == ORA_SOLID) {
+      rho_out[c] = 0.0;
+      for (a = 0; a < 3; ++a) u_out[(int64_t)a * N + c] = 0.0;
+      continue;
+    }
+    for (i = 0; i < L.q; ++i) {
+      double fi = f[(int64_t)i * N + c];
+      r += fi;
+      for (a = 0; a < 3; ++a) j[a] += fi * L.xi[i][a];
+    }
+    rho_out[c] = r;
+    for (a = 0; a < 3; ++a) u_out[(int64_t)a * N + c] = j[a] / r;
+  }
+}
+
+int ora_sizeof_grid(void) { return (int)sizeof(ora_grid); }

@@ -1,0 +1,227 @@
+"""Benchmark of the fused pull-stream + Hermite-regularized collision sweep.
+
+Workload (the headline): D3Q19, 256^3 periodic cells, 3D Taylor-Green
+vortex at U = 0.1 cs plus a Gaussian acoustic pulse (1e-3 rho0, sigma 8
+cells), tau = 0.52, FP32 arithmetic with FP32 population storage; synthetic
+fields generated on the host, resident in HBM before timing.  One step is one
+sweep over the whole grid (pull, moments, regularized collision, store).
+
+Prints one JSON line: MLUPS (whole job), the HBM roofline of the sweep kernel
+(algorithmic bytes 2 q sizeof(storage) per cell update over the kernel time
+measured with HIP events on the launch stream), the FP16-shifted storage
+variant with its speedup, the precision of FP32 / FP16-shifted storage
+against the FP64 build (which matches the oracle to 1e-12), and the FP64 CPU
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS & % HBM roofline (D3Q19 256³); p50/p99 latency, batched serving"
+SOURCES = ["kernels.hip", "kernels.hpp", "lattice.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for s in SOURCES:
+        with open(os.path.join(ROOT, "paper_1710_02065_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0):
+    rho, u = fields
+    sim = lbm.Simulation(lattice=19, shape=(n, n, n), tau=0.52, storage=storage, block=block)
+    sim.init(rho, u)
+    sim.step(warmup)
+    sim.sync()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    sim.sync()
+    ms = t0.elapsed_time(t1)
+    return sim, ms
+
+
+def pressure_error(sim, ref_rho, rho0=1.0):
+    r, u = sim.moments()
+    cs2 = 1.0 / 3.0
+    p = cs2 * (r - rho0)
+    pref = cs2 * (ref_rho - rho0)
+    return float(((p - pref).norm() / pref.norm()).item()), r, u
+
+
+def cpu_baseline(n, seconds):
+    """The FP64 oracle on the host cores over the same 256^3 workload:
+    initialisation, then whole-grid steps until `seconds` have elapsed."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1710_02065_amd import workloads as W
+    U = 0.1 / math.sqrt(3)
+    rho, u = W.taylor_green_3d(n, U, pulse_amp=1e-3, pulse_sigma=8.0)
+    g = O.Grid(19, n, n, n, tau=0.52).init(rho, u)
+    del rho, u
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        g.step(1)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    cores = min(threads, avail) if threads > 0 else avail
+    return dict(value=round(g.N * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+                sample="FP64 oracle, D3Q19 %d^3 Taylor-Green + pulse, %d whole-grid steps "
+                       "(%.1f s) after initialisation" % (n, steps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU z-slab decomposition is a design note, not a measured path)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1710_02065_amd import lbm
+    from paper_1710_02065_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    n = args.n
+    N = n ** 3
+    U = 0.1 / math.sqrt(3)
+    log("generating fields %d^3" % n)
+    rho_np, u_np = W.taylor_green_3d(n, U, pulse_amp=1e-3, pulse_sigma=8.0)
+    dev = torch.device("cuda", 0)
+    fields = (torch.from_numpy(rho_np).to(dev), torch.from_numpy(u_np).to(dev))
+    del rho_np, u_np
+
+    if args.copy_calibration:
+        a = torch.empty(2 ** 31 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("timing f32: %d warmup + %d steps" % (args.warmup, args.steps))
+    sim32, ms32 = run_gpu(lbm, torch, "f32", n, args.steps, args.warmup, fields, args.block)
+    mlups32 = N * args.steps / (ms32 * 1e3)
+    bytes_lup = 2 * 19 * 4
+    per_launch_s = ms32 / 1e3 / args.steps
+    achieved = bytes_lup * N / per_launch_s / 1e9
+    traffic = measured_traffic("k_sweep_d3q19_f32_256")
+
+    variants = {}
+    precision = {}
+    if not args.no_variants:
+        log("timing f16s")
+        sim16, ms16 = run_gpu(lbm, torch, "f16s", n, args.steps, args.warmup, fields, args.block)
+        mlups16 = N * args.steps / (ms16 * 1e3)
+        variants["f16s"] = dict(
+            value=round(mlups16, 1), unit="MLUPS", bytes_per_lup=2 * 19 * 2,
+            hbm_gbs=round(2 * 19 * 2 * N / (ms16 / 1e3 / args.steps) / 1e9, 1),
+            speedup_vs_f32=round(mlups16 / mlups32, 3))
+        log("precision reference: f64 build, %d steps" % (args.warmup + args.steps))
+        sim64, ms64 = run_gpu(lbm, torch, "f64", n, args.steps, args.warmup, fields, args.block)
+        variants["f64"] = dict(value=round(N * args.steps / (ms64 * 1e3), 1), unit="MLUPS")
+        r64, u64 = sim64.moments()
+        for name, sim in (("f32", sim32), ("f16s", sim16)):
+            perr, r, u = pressure_error(sim, r64)
+            precision[name] = dict(
+                horizon_steps=args.warmup + args.steps,
+                acoustic_pressure_rel_l2=perr,
+                rho_max_abs=float((r - r64).abs().max().item()),
+                u_rel_l2=float(((u - u64).norm() / u64.norm()).item()))
+        del sim64, sim16, r64, u64
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups32, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D3Q19 %d^3 periodic, Taylor-Green U=0.1cs + Gaussian pulse 1e-3 "
+                        "sigma 8, tau 0.52, FP32 storage (fused pull + rrBGK sweep)" % n,
+            "lattice": "D3Q19", "cells": N, "storage": "f32", "tau": 0.52,
+            "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_lup * N,
+            "kernel": "k_sweep<D3Q19, f32>"},
+    }
+    if variants:
+        out["variants"] = variants
+    if precision:
+        out["precision_vs_f64_build"] = precision
+    del sim32
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

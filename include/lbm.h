@@ -1,0 +1,221 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) Hermite-regularized lattice Boltzmann
+ * library.
+ *
+ * The method is the recursive-regularized BGK scheme ("rrBGK") of Brogi,
+ * Malaspinas, Chopard & Bonadonna, "Hermite regularization of the Lattice
+ * Boltzmann Method for open source computational aeroacoustics"
+ * (arXiv:1710.02065), Sec. II:
+ *   - Sec. II.A, eq. (optimizedLB): each step streams the populations and
+ *     replaces them by f^{eqH}(rho, u) + (1 - 1/tau) f^{neqH}, both rebuilt
+ *     from rho, u and the non-equilibrium second moment a2_neq through the
+ *     Hermite recursions eqs. (recursive1), (recursive2), up to third order;
+ *   - Sec. II.C, eqs. (spongeLB), (dampingLBM), (modifiedMoments): an
+ *     absorbing layer that adds chi (f^{eqH}(rho_ref, u_ref) - f^{eqH}(rho*, u*))
+ *     with the polynomial profile sigma(x) printed at the end of Sec. II.C;
+ *   - Sec. II.B: 2:1 multi-domain grid refinement (two levels).
+ * Boundary rules (Sec. III and IV setups): halfway bounce-back walls,
+ * free-slip faces, zero-gradient outflow faces, equilibrium inlet cells.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1 on the coarsest level, cs^2 = 1/3.
+ *   - Cells are indexed c = (z*ny + y)*nx + x, x fastest; nz = 1 in 2D.
+ *   - Direction order (documented contract; lbm_lattice_table returns it):
+ *       0: rest; then opposite pairs (2k-1, 2k):
+ *       1,2 = (+-1,0,0)  3,4 = (0,+-1,0)  5,6 = (0,0,+-1)         [D3Qx]
+ *       D2Q9 after the four axes: 5,6 = +-(1,1)  7,8 = +-(1,-1)
+ *       D3Q19/27 edges: 7,8 = +-(1,1,0)  9,10 = +-(1,-1,0)
+ *                       11,12 = +-(1,0,1)  13,14 = +-(1,0,-1)
+ *                       15,16 = +-(0,1,1)  17,18 = +-(0,1,-1)
+ *       D3Q27 corners: 19,20 = +-(1,1,1)  21,22 = +-(1,1,-1)
+ *                      23,24 = +-(1,-1,1)  25,26 = +-(-1,1,1)
+ *   - State: the library stores post-collision populations f*(x, t); one
+ *     step pulls f(x, t+1) = f*(x - xi_i, t) and collides it.
+ *   - Every pointer argument documented as "device" must be memory of the
+ *     context's device (for example a torch CUDA tensor's data_ptr()); the
+ *     call only enqueues work on the context's stream and returns.  Host
+ *     pointers are read before the call returns.
+ *   - No call throws.  Every int-returning call returns LBM_OK or a negative
+ *     status; lbm_last_error() gives a thread-local message.  A context is
+ *     not thread-safe; distinct contexts are independent.
+ */
+#ifndef HRLBM_LBM_H
+#define HRLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+/* lattices (Sec. II.A Gauss-Hermite quadratures) */
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
+
+/* population storage.  F64: FP64 storage and FP64 arithmetic (verification
+ * build).  F32: FP32 storage of f.  F32S / F16S: FP32 / IEEE binary16
+ * storage of the shifted value f_i - w_i rho0 (round to nearest even).
+ * Every non-F64 format computes in FP32 on the deviation from rest. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3 };
+
+/* face rules, per face in the order x-, x+, y-, y+, z-, z+.  Both faces of
+ * an axis are periodic or neither is.
+ *   PERIODIC: wrap-around.
+ *   FREESLIP: specular reflection, wall half a cell outside the face row.
+ *   OUTFLOW:  zero gradient, a population entering through the face is
+ *             copied from the face row. */
+enum { LBM_PERIODIC = 0, LBM_FREESLIP = 1, LBM_OUTFLOW = 2 };
+
+/* cell kinds in the mask.
+ *   FLUID: streamed and collided.
+ *   SOLID: never updated; links from a fluid cell into a solid cell are
+ *          bounced back halfway (wall at rest).
+ *   INLET: holds f^{eqH}(rho0, U u_dir (1 + inlet_noise r)) with r uniform
+ *          in [-1, 1) per component, r = (z >> 40) * 2^-23 - 1 where z is the
+ *          k-th SplitMix64 output for `seed` (Steele, Lea & Flood 2014),
+ *          k = ((t*2 + level)*N_level + cell)*3 + component, t = time index
+ *          (on that level) of the state being produced. */
+enum { LBM_FLUID = 0, LBM_SOLID = 1, LBM_INLET = 2 };
+
+/* status codes */
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument or configuration */
+  LBM_ENOMEM = -2,      /* device allocation failed / bound buffer too small */
+  LBM_EDEVICE = -3,     /* HIP runtime error */
+  LBM_EUNSTABLE = -4,   /* a non-finite or non-positive density was seen */
+  LBM_ESTATE = -5,      /* call out of order (e.g. step before init) */
+  LBM_EUNSUPPORTED = -6 /* valid request this build does not implement */
+};
+
+/* flags */
+#define LBM_ALLOW_HIGH_MA 0x1u /* accept Ma > 0.6 (beyond the stable range
+                                  reported in the paper's conclusions) */
+#define LBM_NO_GRAPH 0x2u      /* never replay step sequences as hipGraphs */
+
+typedef struct lbm_config {
+  uint32_t struct_size;  /* sizeof(lbm_config); set by lbm_config_init */
+  int32_t lattice;       /* LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 */
+  int32_t storage;       /* LBM_F64, LBM_F32, LBM_F32S, LBM_F16S */
+  int32_t device;        /* HIP device ordinal */
+  int64_t nx, ny, nz;    /* coarse grid; nz must be 1 for D2Q9 */
+  double tau;            /* coarse relaxation time; nu = cs^2 (tau - 1/2) */
+  double rho0;           /* rest density (also the storage shift) */
+  double ma;             /* inlet Mach number: U = ma * cs along u_dir */
+  double u_dir[3];       /* inlet direction (need not be normalised) */
+  int32_t face_bc[6];    /* LBM_PERIODIC / LBM_FREESLIP / LBM_OUTFLOW */
+  int32_t sponge_width[6]; /* absorbing-layer width in coarse cells, per face */
+  double chi_max;        /* sponge strength maximum, 0 <= chi_max < 4 tau */
+  double rho_ref;        /* sponge reference density */
+  double u_ref[3];       /* sponge reference velocity */
+  int64_t refine_lo[3];  /* refined coarse-node box [lo, hi]; lo == hi == 0 */
+  int64_t refine_hi[3];  /*   on every axis means no refinement */
+  uint64_t seed;         /* inlet noise seed */
+  double inlet_noise;    /* relative inlet velocity noise amplitude */
+  void* stream;          /* hipStream_t for all work; NULL = null stream */
+  uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH */
+  uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
+} lbm_config;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *cfg with defaults: D3Q19, F32, device 0, 64^3 periodic, tau 0.6,
+ * rho0 1, ma 0, u_dir (1,0,0), no sponge, no refinement, rho_ref 1. */
+void lbm_config_init(lbm_config* cfg);
+
+/* Device bytes lbm_create would allocate for this configuration (both
+ * population buffers of every level, mask, interface buffers).  0 on an
+ * invalid configuration (see lbm_last_error). */
+size_t lbm_required_bytes(const lbm_config* cfg);
+
+/* Validate the configuration and create a context.  Rejects: tau <= 1/2
+ * (nu = cs^2 (tau - 1/2) must be positive, Sec. II.A); chi_max >= 4 tau on
+ * any level (the stability bound of Sec. II.C); ma > 0.6 without
+ * LBM_ALLOW_HIGH_MA; unknown lattice or storage; grids above 2^31 - 1 cells;
+ * a refinement box that is not at least 4 coarse cells away from every
+ * non-periodic face or is smaller than 4 cells per axis.  No device memory
+ * is allocated here: the first lbm_init allocates it unless lbm_bind_memory
+ * was called before.  *out receives the context. */
+int lbm_create(const lbm_config* cfg, lbm_ctx** out);
+
+/* Use a caller-owned device buffer of at least lbm_required_bytes bytes for
+ * all context memory.  Must be called before lbm_init.  The library never
+ * frees it; the caller keeps it alive until lbm_destroy. */
+int lbm_bind_memory(lbm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Write the post-collision state at t = 0 of `level` (0 = coarse, 1 = fine):
+ *   f*_i = f^{eqH}_i(rho, u) + (1 - 1/tau) f^{neqH}_i(a2_neq = pi_neq, u)
+ * (eqs. eqH, neqH).  Device pointers, FP64, structure of arrays over the
+ * level's cells: rho [N], u [3][N], pi_neq [6][N] in the order
+ * (xx, yy, zz, xy, xz, yz); z entries are ignored in 2D.  Any of them may be
+ * NULL: rho0, the inlet velocity U u_dir, zero.  mask [N] uint8 device
+ * pointer of LBM_FLUID/SOLID/INLET, NULL = all fluid; it is copied.  Resets
+ * the step counter of the whole context.  Inputs may be freed once the
+ * stream has passed this point. */
+int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
+             const double* pi_neq, const uint8_t* mask);
+
+/* Enqueue n coarse steps (each is two fine substeps on a refined context).
+ * Returns after enqueueing.  Kernel-side instability is recorded in a sticky
+ * flag reported by lbm_sync / lbm_moments. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Wait for the context's stream; return LBM_OK or the sticky
+ * LBM_EUNSTABLE / LBM_EDEVICE. */
+int lbm_sync(lbm_ctx* ctx);
+
+/* Steps completed (coarse time index). */
+int64_t lbm_time(const lbm_ctx* ctx);
+
+/* Grid shape of a level. */
+int lbm_level_shape(const lbm_ctx* ctx, int level, int64_t* nx, int64_t* ny,
+                    int64_t* nz);
+
+/* Density and velocity of the current stored state of `level`:
+ * rho = sum_i f*_i, u = sum_i f*_i xi_i / rho (eq. moments).  Away from the
+ * sponge these equal the pre-collision moments of the same time level
+ * (the collision conserves them).  SOLID cells report 0.  Device FP64
+ * outputs rho_out [N] and u_out [3][N] (either may be NULL).  Returns the
+ * sticky instability status as lbm_sync does, without synchronising. */
+int lbm_moments(lbm_ctx* ctx, int level, double* rho_out, double* u_out);
+
+/* Density (as lbm_moments) at n cells of `level`: cells [n] int64 device
+ * pointer of cell indices, rho_out [n] FP64 device pointer. */
+int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n,
+              double* rho_out);
+
+/* Canonical FP64 copy of the stored populations of `level`, [q][N] in the
+ * documented direction order, unshifted (device pointers).  Used for
+ * checkpoint/resume and parity checks.  set also resets nothing else:
+ * the step counter is kept. */
+int lbm_get_populations(lbm_ctx* ctx, int level, double* out);
+int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
+
+/* Serving: advance ctxs[k] by steps[k] coarse steps, k < n, sharing
+ * launches between contexts.  All contexts must be unrefined, on one device
+ * and one stream, and initialised.  Each context's result is bitwise the
+ * same as lbm_step(ctxs[k], steps[k]) alone. */
+int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
+
+/* Time the sweep for each candidate workgroup size on this context's
+ * current state (the state is restored afterwards), keep the fastest, and
+ * return it (> 0) or a negative status. */
+int lbm_autotune(lbm_ctx* ctx, int trials);
+
+/* Release the context and the memory it allocated.  NULL-safe. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Velocity table of a lattice in the documented order: xi [q][3] int32,
+ * w [q] FP64 (host pointers; either may be NULL).  Returns q or LBM_EINVAL. */
+int lbm_lattice_table(int lattice, int32_t* xi, double* w);
+
+/* Thread-local description of the last error on this thread. */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRLBM_LBM_H */

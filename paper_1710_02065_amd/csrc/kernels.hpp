@@ -1,0 +1,374 @@
+// Device code of the fused pull-stream + Hermite-regularized collision sweep
+// and its companion kernels (initialisation, moments, probes, population
+// import/export).
+//
+// One thread updates one cell.  Populations are structure-of-arrays,
+// buf[i * P + c] with c = (z*ny + y)*nx + x, so a wavefront's 64 lanes read
+// 64 consecutive cells of one population: every load and store is coalesced,
+// and the pull offsets xi_i shift the addresses by whole rows/planes or by
+// one element.  The step is bound by HBM bandwidth (read q, write q values
+// per cell); there is no dense contraction, so no matrix cores are used.
+//
+// All non-FP64 formats compute in FP32 on deviations from the rest state
+// h_i = f_i - w_i rho0, so the moments are sums of small numbers:
+//   drho = sum h_i, j = sum h_i xi_i, P = sum h_i xi_i xi_i = Pi - rho0 cs^2 I.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace hrlbm {
+
+enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
+enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2 };
+
+// ------------------------------------------------------------------------
+// Division of 32-bit unsigned numbers below 2^31 by a run-time invariant
+// divisor with one multiply-high, add and shift (Granlund & Montgomery,
+// "Division by invariant integers using multiplication", PLDI 1994).
+// ------------------------------------------------------------------------
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{d, (uint32_t)m, l};
+}
+
+__host__ __device__ inline uint32_t fast_div(uint32_t n, const FastDiv& f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t t = __umulhi(n, f.m);
+#else
+  const uint32_t t = (uint32_t)(((uint64_t)n * f.m) >> 32);
+#endif
+  return (t + n) >> f.s;
+}
+
+// ------------------------------------------------------------------------
+// Storage formats
+// ------------------------------------------------------------------------
+struct StoreF64 {
+  using T = double;
+  using R = double;
+  static constexpr bool kShifted = false;
+};
+struct StoreF32 {
+  using T = float;
+  using R = float;
+  static constexpr bool kShifted = false;
+};
+struct StoreF32S {
+  using T = float;
+  using R = float;
+  static constexpr bool kShifted = true;
+};
+struct StoreF16S {
+  using T = _Float16;
+  using R = float;
+  static constexpr bool kShifted = true;
+};
+
+// stored value -> deviation h = f - w rho0
+template <class S>
+__device__ __forceinline__ typename S::R decode(typename S::T v,
+                                                typename S::R wrho0) {
+  using R = typename S::R;
+  if constexpr (S::kShifted)
+    return (R)v;
+  else
+    return (R)v - wrho0;
+}
+// deviation -> stored value (round to nearest even for narrowing formats)
+template <class S>
+__device__ __forceinline__ typename S::T encode(typename S::R h,
+                                                typename S::R wrho0) {
+  using T = typename S::T;
+  if constexpr (S::kShifted)
+    return (T)h;
+  else
+    return (T)(h + wrho0);
+}
+
+// ------------------------------------------------------------------------
+// Kernel arguments
+// ------------------------------------------------------------------------
+template <class S>
+struct SweepArgs {
+  using T = typename S::T;
+  using R = typename S::R;
+  const T* src;          // post-collision state at t
+  T* dst;                // post-collision state at t + 1
+  const uint8_t* mask;   // nullptr = all fluid
+  int* status;           // sticky instability flag
+  uint32_t nx, ny, nz, ncell;
+  uint64_t pstride;      // population stride P >= ncell
+  FastDiv div_nx, div_ny;
+  R omega1;              // 1 - 1/tau
+  R rho0;
+  R chi_max, rho_ref, uref[3];
+  R uin[3], noise;
+  int32_t face[6];
+  int32_t sponge[6];
+  uint64_t seed;
+  uint64_t t_new;        // time index of the state being produced
+  int32_t level;
+  uint32_t ntiles;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Re-map the hardware workgroup id so that each XCD walks one
+// contiguous range of tiles: cache lines shared by neighbouring tiles then
+// stay within one L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t per = n / kXcd, rem = n % kXcd;
+  const uint32_t x = b % kXcd, k = b / kXcd;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// ------------------------------------------------------------------------
+// Regularized rebuild (eqs. eqH, neqH, optimizedLB) from Hermite
+// coefficients.  With the combined coefficients
+//   m0 (scalar), m1 (vector), m2 (symmetric), m3 (third-order set)
+// the deviation from rest of every population is
+//   h_i = w_i [ m0 + xi.m1 / cs^2 + H2(xi):m2 / (2 cs^4)
+//              + sum_k H_k(xi) c_k(m3) / N_k ].
+// ------------------------------------------------------------------------
+template <class L, class R>
+struct Coeffs {
+  R m0;
+  R m1[3];
+  R m2[6];  // xx, yy, zz, xy, xz, yz
+  R m3[7];  // xxy, xyy, xxz, xzz, yyz, yzz, xyz
+};
+
+template <class L, class R>
+__device__ __forceinline__ R rebuild_one(const Coeffs<L, R>& c, R bk[L::K],
+                                         int i) {
+  constexpr R inv_cs2 = (R)3.0, half_inv_cs4 = (R)4.5;
+  const Dir v = L::dir(i);
+  R s = c.m0;
+  R lin = (R)0;
+  if (v.x) lin += (R)v.x * c.m1[0];
+  if (v.y) lin += (R)v.y * c.m1[1];
+  if (L::D == 3 && v.z) lin += (R)v.z * c.m1[2];
+  s += inv_cs2 * lin;
+  // H2(xi):m2 = sum_ab xi_a xi_b m2_ab - cs^2 tr(m2)
+  R tr = c.m2[0] + c.m2[1] + (L::D == 3 ? c.m2[2] : (R)0);
+  R q2 = -(R)kCs2 * tr;
+  if (v.x) q2 += c.m2[0];
+  if (v.y) q2 += c.m2[1];
+  if (L::D == 3 && v.z) q2 += c.m2[2];
+  if (v.x * v.y) q2 += (R)(2 * v.x * v.y) * c.m2[3];
+  if (L::D == 3 && v.x * v.z) q2 += (R)(2 * v.x * v.z) * c.m2[4];
+  if (L::D == 3 && v.y * v.z) q2 += (R)(2 * v.y * v.z) * c.m2[5];
+  s += half_inv_cs4 * q2;
+#pragma unroll
+  for (int k = 0; k < L::K; ++k) {
+    const double hk = basis_h<L>(i, k);
+    if (hk != 0.0) s += (R)hk * bk[k];
+  }
+  return (R)L::w(i) * s;
+}
+
+// third-order set -> basis coefficients c_k / N_k
+template <class L, class R>
+__device__ __forceinline__ void basis_coeffs(const R m3[7], R bk[L::K]) {
+#pragma unroll
+  for (int k = 0; k < L::K; ++k) {
+    const Basis3 b = L::basis(k);
+    R v = (R)b.sgn[0] * m3[b.idx[0]];
+    if (b.n == 2) v += (R)b.sgn[1] * m3[b.idx[1]];
+    bk[k] = v * (R)(1.0 / basis_norm<L>(k));
+  }
+}
+
+// third-order tensor components of the product v_a w_b w_c symmetrised as
+// in the recursion: returns t_abc = u_a A_bc + u_b A_ac + u_c A_ab for the
+// seven packed components.  A in (xx, yy, zz, xy, xz, yz).
+template <class R>
+__device__ __forceinline__ void recursion3(const R u[3], const R A[6], R t[7]) {
+  // A_ab accessor
+  const R xx = A[0], yy = A[1], zz = A[2], xy = A[3], xz = A[4], yz = A[5];
+  t[kXXY] = (R)2 * u[0] * xy + u[1] * xx;
+  t[kXYY] = (R)2 * u[1] * xy + u[0] * yy;
+  t[kXXZ] = (R)2 * u[0] * xz + u[2] * xx;
+  t[kXZZ] = (R)2 * u[2] * xz + u[0] * zz;
+  t[kYYZ] = (R)2 * u[1] * yz + u[2] * yy;
+  t[kYZZ] = (R)2 * u[2] * yz + u[1] * zz;
+  t[kXYZ] = u[0] * yz + u[1] * xz + u[2] * xy;
+}
+
+// rho u_a u_b u_c for the seven packed components
+template <class R>
+__device__ __forceinline__ void cube3(R rho, const R u[3], R t[7]) {
+  const R ruu_x = rho * u[0], ruu_y = rho * u[1];
+  t[kXXY] = ruu_x * u[0] * u[1];
+  t[kXYY] = ruu_x * u[1] * u[1];
+  t[kXXZ] = ruu_x * u[0] * u[2];
+  t[kXZZ] = ruu_x * u[2] * u[2];
+  t[kYYZ] = ruu_y * u[1] * u[2];
+  t[kYZZ] = ruu_y * u[2] * u[2];
+  t[kXYZ] = ruu_x * u[1] * u[2];
+}
+
+// Collision of one cell (eq. optimizedLB, with eqs. spongeLB/dampingLBM and
+// the modified moments at n = m = 1/2 where chi > 0).  h: pre-collision
+// deviations; out: post-collision deviations.  Returns rho* for the
+// stability watchdog.
+template <class L, class R, bool kSponge>
+__device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
+                                     R rho_ref, const R uref[3],
+                                     R out[L::Q]) {
+  constexpr int Q = L::Q;
+  R drho = (R)0, j[3] = {(R)0, (R)0, (R)0};
+  R P[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const Dir v = L::dir(i);
+    drho += h[i];
+    if (v.x) j[0] += (R)v.x * h[i];
+    if (v.y) j[1] += (R)v.y * h[i];
+    if (L::D == 3 && v.z) j[2] += (R)v.z * h[i];
+    if (v.x) P[0] += h[i];
+    if (v.y) P[1] += h[i];
+    if (L::D == 3 && v.z) P[2] += h[i];
+    if (v.x * v.y) P[3] += (R)(v.x * v.y) * h[i];
+    if (L::D == 3 && v.x * v.z) P[4] += (R)(v.x * v.z) * h[i];
+    if (L::D == 3 && v.y * v.z) P[5] += (R)(v.y * v.z) * h[i];
+  }
+  if constexpr (kSponge) {
+    if (chi != (R)0) {
+      const R k = (R)1 / ((R)1 + (R)0.5 * chi);
+      drho = (drho + (R)0.5 * chi * (rho_ref - rho0)) * k;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) j[a] = (j[a] + (R)0.5 * chi * rho_ref * uref[a]) * k;
+    }
+  }
+  const R rho = rho0 + drho;
+  const R irho = (R)1 / rho;
+  R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
+  // a2_neq = Pi - rho cs^2 I - rho u u  (Pi - rho0 cs^2 I = P)
+  R a2[6];
+  a2[0] = P[0] - (R)kCs2 * drho - j[0] * u[0];
+  a2[1] = P[1] - (R)kCs2 * drho - j[1] * u[1];
+  a2[2] = L::D == 3 ? P[2] - (R)kCs2 * drho - j[2] * u[2] : (R)0;
+  a2[3] = P[3] - j[0] * u[1];
+  a2[4] = L::D == 3 ? P[4] - j[0] * u[2] : (R)0;
+  a2[5] = L::D == 3 ? P[5] - j[1] * u[2] : (R)0;
+
+  Coeffs<L, R> c;
+  R a3n[7], a3e[7];
+  recursion3<R>(u, a2, a3n);
+  cube3<R>(rho, u, a3e);
+  if constexpr (kSponge) {
+    // post = (1 - chi) E(rho*, u) + chi E(rho_ref, u_ref) + omega1 N
+    const R e = (R)1 - chi;
+    c.m0 = e * drho + chi * (rho_ref - rho0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c.m1[a] = e * j[a] + chi * rho_ref * uref[a];
+    const R ru[3] = {rho_ref * uref[0], rho_ref * uref[1], rho_ref * uref[2]};
+    c.m2[0] = e * j[0] * u[0] + chi * ru[0] * uref[0] + omega1 * a2[0];
+    c.m2[1] = e * j[1] * u[1] + chi * ru[1] * uref[1] + omega1 * a2[1];
+    c.m2[2] = e * j[2] * u[2] + chi * ru[2] * uref[2] + omega1 * a2[2];
+    c.m2[3] = e * j[0] * u[1] + chi * ru[0] * uref[1] + omega1 * a2[3];
+    c.m2[4] = e * j[0] * u[2] + chi * ru[0] * uref[2] + omega1 * a2[4];
+    c.m2[5] = e * j[1] * u[2] + chi * ru[1] * uref[2] + omega1 * a2[5];
+    R a3r[7];
+    cube3<R>(rho_ref, uref, a3r);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) c.m3[k] = e * a3e[k] + chi * a3r[k] + omega1 * a3n[k];
+  } else {
+    c.m0 = drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c.m1[a] = j[a];
+    c.m2[0] = j[0] * u[0] + omega1 * a2[0];
+    c.m2[1] = j[1] * u[1] + omega1 * a2[1];
+    c.m2[2] = j[2] * u[2] + omega1 * a2[2];
+    c.m2[3] = j[0] * u[1] + omega1 * a2[3];
+    c.m2[4] = j[0] * u[2] + omega1 * a2[4];
+    c.m2[5] = j[1] * u[2] + omega1 * a2[5];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
+  }
+  R bk[L::K];
+  basis_coeffs<L, R>(c.m3, bk);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i] = rebuild_one<L, R>(c, bk, i);
+  return rho;
+}
+
+// Deviations of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u) (initial state and
+// inlet cells), rho given as its deviation drho from rho0.
+template <class L, class R>
+__device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
+                                              const R a2[6], R omega1,
+                                              R out[L::Q]) {
+  const R rho = rho0 + drho;
+  Coeffs<L, R> c;
+  c.m0 = drho;
+  const R j[3] = {rho * u[0], rho * u[1], rho * u[2]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.m1[a] = j[a];
+  c.m2[0] = j[0] * u[0] + omega1 * a2[0];
+  c.m2[1] = j[1] * u[1] + omega1 * a2[1];
+  c.m2[2] = j[2] * u[2] + omega1 * a2[2];
+  c.m2[3] = j[0] * u[1] + omega1 * a2[3];
+  c.m2[4] = j[0] * u[2] + omega1 * a2[4];
+  c.m2[5] = j[1] * u[2] + omega1 * a2[5];
+  R a3n[7], a3e[7];
+  recursion3<R>(u, a2, a3n);
+  cube3<R>(rho, u, a3e);
+#pragma unroll
+  for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
+  R bk[L::K];
+  basis_coeffs<L, R>(c.m3, bk);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) out[i] = rebuild_one<L, R>(c, bk, i);
+}
+
+// ------------------------------------------------------------------------
+// Absorbing-layer strength (Sec. II.C profile), analytic in the coordinates:
+// chi = chi_max * max over faces of 3125 (L - s)(s - s0)^4 / (256 (L - s0)^5)
+// with s the coordinate normal to the face (mirrored on low faces),
+// s0 = n - W and L = n.
+// ------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R sponge_chi(const int32_t* width, R chi_max,
+                                        uint32_t x, uint32_t y, uint32_t z,
+                                        uint32_t nx, uint32_t ny, uint32_t nz) {
+  const uint32_t pos[3] = {x, y, z}, n[3] = {nx, ny, nz};
+  R best = (R)0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int32_t W = width[f];
+    if (W <= 0) continue;
+    const int a = f >> 1;
+    const R s = (f & 1) ? (R)pos[a] : (R)(n[a] - 1u - pos[a]);
+    const R s0 = (R)(int64_t)(n[a] - (uint32_t)W);
+    if (s < s0) continue;
+    const R Lw = (R)W;
+    const R d = (s - s0) / Lw;
+    const R sig = (R)(3125.0 / 256.0) * ((R)1 - d) * (d * d) * (d * d);
+    best = sig > best ? sig : best;
+  }
+  return chi_max * best;
+}
+
+// SplitMix64 output k of the generator seeded with `seed` (Steele, Lea &
+// Flood, OOPSLA 2014), mapped to [-1, 1) with 2^-23 spacing.
+__device__ __forceinline__ float splitmix_pm1(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (float)(uint32_t)(z >> 40) * (1.0f / 8388608.0f) - 1.0f;
+}
+
+}  // namespace hrlbm

@@ -1,0 +1,135 @@
+// Compile-time lattice descriptions for the HIP kernels.
+//
+// D2Q9, D3Q19 and D3Q27 are the Gauss-Hermite quadratures the paper uses
+// (Sec. II.A).  Directions follow the order documented in include/lbm.h:
+// rest first, then opposite pairs (2k-1, 2k).  Velocities are generated from
+// a single ordered list of the 26 non-rest unit-cube directions; D2Q9 takes
+// the in-plane subset in the same pairing.
+//
+// The third-order Hermite terms each lattice can carry (Sec. II.A: D2Q9 and
+// D3Q27 resolve the xxy-type and xyz polynomials; D3Q19 only resolves the
+// sums and differences of the pairs xxy/yzz, xyy/xzz, xxz/yyz) are exposed
+// as a short basis with compile-time values H_k(xi_i) and norms
+// N_k = sum_i w_i H_k(xi_i)^2.
+#pragma once
+
+#include <cstdint>
+
+namespace hrlbm {
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// 26 directions of the 3x3x3 stencil, paired as (+v, -v)
+struct Dir {
+  int x, y, z;
+};
+constexpr Dir kDirs3[27] = {
+    {0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},
+    {0, 0, 1},   {0, 0, -1},  {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
+    {-1, 1, 0},  {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+    {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},  {1, 1, 1},
+    {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1},
+    {-1, 1, 1},  {1, -1, -1}};
+constexpr Dir kDirs2[9] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0},
+                           {0, 1, 0},  {0, -1, 0},  {1, 1, 0},
+                           {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+
+// third-order Hermite polynomial H_abc at integer velocity v
+constexpr double h3(const Dir& v, int a, int b, int c) {
+  const int comp[3] = {v.x, v.y, v.z};
+  const double xa = comp[a], xb = comp[b], xc = comp[c];
+  return xa * xb * xc -
+         kCs2 * (xa * (b == c ? 1 : 0) + xb * (a == c ? 1 : 0) +
+                 xc * (a == b ? 1 : 0));
+}
+
+// Indices into the packed third-order coefficient set
+//   {xxy, xyy, xxz, xzz, yyz, yzz, xyz}
+enum A3 { kXXY = 0, kXYY, kXXZ, kXZZ, kYYZ, kYZZ, kXYZ };
+constexpr int kA3Idx[7][3] = {{0, 0, 1}, {0, 1, 1}, {0, 0, 2}, {0, 2, 2},
+                              {1, 1, 2}, {1, 2, 2}, {0, 1, 2}};
+
+// A basis element: sum_j s_j H_{idx_j}, up to two packed components.
+struct Basis3 {
+  int n;
+  int idx[2];
+  int sgn[2];
+};
+
+template <int Q>
+struct Lattice;
+
+template <>
+struct Lattice<9> {
+  static constexpr int Q = 9, D = 2, K = 2;
+  static constexpr Dir dir(int i) { return kDirs2[i]; }
+  static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  static constexpr Basis3 basis(int k) {
+    return k == 0 ? Basis3{1, {kXXY, 0}, {1, 0}} : Basis3{1, {kXYY, 0}, {1, 0}};
+  }
+};
+
+template <>
+struct Lattice<19> {
+  static constexpr int Q = 19, D = 3, K = 6;
+  static constexpr Dir dir(int i) { return kDirs3[i]; }
+  static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  // (xxy +- yzz), (xyy +- xzz), (xxz +- yyz)
+  static constexpr Basis3 basis(int k) {
+    return k == 0   ? Basis3{2, {kXXY, kYZZ}, {1, 1}}
+           : k == 1 ? Basis3{2, {kXXY, kYZZ}, {1, -1}}
+           : k == 2 ? Basis3{2, {kXYY, kXZZ}, {1, 1}}
+           : k == 3 ? Basis3{2, {kXYY, kXZZ}, {1, -1}}
+           : k == 4 ? Basis3{2, {kXXZ, kYYZ}, {1, 1}}
+                    : Basis3{2, {kXXZ, kYYZ}, {1, -1}};
+  }
+};
+
+template <>
+struct Lattice<27> {
+  static constexpr int Q = 27, D = 3, K = 7;
+  static constexpr Dir dir(int i) { return kDirs3[i]; }
+  static constexpr double w(int i) {
+    return i == 0 ? 8.0 / 27.0
+                  : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+  }
+  static constexpr Basis3 basis(int k) { return Basis3{1, {k, 0}, {1, 0}}; }
+};
+
+// value of basis element k at direction i
+template <class L>
+constexpr double basis_h(int i, int k) {
+  const Basis3 b = L::basis(k);
+  double s = 0.0;
+  for (int j = 0; j < b.n; ++j)
+    s += b.sgn[j] * h3(L::dir(i), kA3Idx[b.idx[j]][0], kA3Idx[b.idx[j]][1],
+                       kA3Idx[b.idx[j]][2]);
+  return s;
+}
+
+// lattice norm N_k = sum_i w_i H_k(xi_i)^2, evaluated at compile time
+template <class L>
+constexpr double basis_norm(int k) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::w(i) * basis_h<L>(i, k) * basis_h<L>(i, k);
+  return s;
+}
+
+template <class L>
+constexpr int opposite(int i) {
+  return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+}
+
+// direction index of velocity (x, y, z) in lattice L, -1 if absent
+template <class L>
+constexpr int find_dir(int x, int y, int z) {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::dir(i).x == x && L::dir(i).y == y && L::dir(i).z == z) return i;
+  return -1;
+}
+
+}  // namespace hrlbm

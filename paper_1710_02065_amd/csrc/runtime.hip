@@ -1,0 +1,648 @@
+// Host runtime behind the C ABI of include/lbm.h: configuration checks,
+// device memory layout, the step loop (with hipGraph replay of step
+// sequences), observables and population import/export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lattice.hpp"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace hrlbm {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int lattice_dim(int lattice) { return lattice == LBM_D2Q9 ? 2 : 3; }
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32:
+    case LBM_F32S: return 4;
+    case LBM_F16S: return 2;
+  }
+  return 0;
+}
+
+// Population stride: a multiple of 128 elements, plus 128 so that large
+// power-of-two grids do not put every population at the same offset
+// modulo the HBM channel interleave.
+uint64_t pop_stride(uint64_t n) {
+  uint64_t p = align_up(n, 128);
+  if (n >= (1u << 20)) p += 128;
+  return p;
+}
+
+static bool refined(const lbm_config& c) {
+  for (int a = 0; a < 3; ++a)
+    if (c.refine_lo[a] != 0 || c.refine_hi[a] != 0) return true;
+  return false;
+}
+
+static double inlet_speed(const lbm_config& c) {
+  return c.ma * std::sqrt(1.0 / 3.0);
+}
+
+// U * u_dir / |u_dir|
+static void inlet_velocity(const lbm_config& c, double u[3]) {
+  double n = std::sqrt(c.u_dir[0] * c.u_dir[0] + c.u_dir[1] * c.u_dir[1] +
+                       c.u_dir[2] * c.u_dir[2]);
+  const double U = inlet_speed(c);
+  for (int a = 0; a < 3; ++a) u[a] = n > 0 ? U * c.u_dir[a] / n : 0.0;
+  if (c.lattice == LBM_D2Q9) u[2] = 0.0;
+}
+
+int validate(const lbm_config* cfg) {
+  if (!cfg) return set_error(LBM_EINVAL, "config is NULL");
+  const lbm_config& c = *cfg;
+  if (c.struct_size != sizeof(lbm_config))
+    return set_error(LBM_EINVAL, "struct_size %u != %zu (call lbm_config_init)",
+                     c.struct_size, sizeof(lbm_config));
+  if (c.lattice != LBM_D2Q9 && c.lattice != LBM_D3Q19 && c.lattice != LBM_D3Q27)
+    return set_error(LBM_EINVAL, "unknown lattice %d", c.lattice);
+  if (storage_bytes(c.storage) == 0)
+    return set_error(LBM_EINVAL, "unknown storage %d", c.storage);
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1)
+    return set_error(LBM_EINVAL, "grid %lld x %lld x %lld", (long long)c.nx,
+                     (long long)c.ny, (long long)c.nz);
+  if (c.lattice == LBM_D2Q9 && c.nz != 1)
+    return set_error(LBM_EINVAL, "D2Q9 needs nz == 1");
+  const double cells = (double)c.nx * (double)c.ny * (double)c.nz;
+  if (cells > 2147483647.0)
+    return set_error(LBM_EINVAL, "grid has %.0f cells; the limit is 2^31 - 1", cells);
+  if (!(c.tau > 0.5) || !std::isfinite(c.tau))
+    return set_error(LBM_EINVAL, "tau = %g: nu = cs^2 (tau - 1/2) must be > 0", c.tau);
+  if (!(c.rho0 > 0)) return set_error(LBM_EINVAL, "rho0 must be > 0");
+  if (!(c.ma >= 0) || (c.ma > 0.6 && !(c.flags & LBM_ALLOW_HIGH_MA)))
+    return set_error(LBM_EINVAL, "Ma = %g outside [0, 0.6] (set LBM_ALLOW_HIGH_MA)", c.ma);
+  if (!(c.chi_max >= 0))
+    return set_error(LBM_EINVAL, "chi_max must be >= 0");
+  for (int a = 0; a < 3; ++a) {
+    const bool p0 = c.face_bc[2 * a] == LBM_PERIODIC, p1 = c.face_bc[2 * a + 1] == LBM_PERIODIC;
+    if (p0 != p1)
+      return set_error(LBM_EINVAL, "axis %d: both faces periodic or neither", a);
+  }
+  for (int f = 0; f < 6; ++f) {
+    if (c.face_bc[f] < LBM_PERIODIC || c.face_bc[f] > LBM_OUTFLOW)
+      return set_error(LBM_EINVAL, "face %d: unknown rule %d", f, c.face_bc[f]);
+    const int64_t n = f < 2 ? c.nx : (f < 4 ? c.ny : c.nz);
+    if (c.sponge_width[f] < 0 || c.sponge_width[f] > n)
+      return set_error(LBM_EINVAL, "face %d: sponge width %d", f, c.sponge_width[f]);
+    if (c.lattice == LBM_D2Q9 && f >= 4 && c.sponge_width[f] != 0)
+      return set_error(LBM_EINVAL, "D2Q9 has no z faces");
+  }
+  if (c.lattice == LBM_D2Q9 && (c.face_bc[4] != LBM_PERIODIC || c.face_bc[5] != LBM_PERIODIC))
+    return set_error(LBM_EINVAL, "D2Q9: z faces must be LBM_PERIODIC");
+  // Sec. II.C: sigma_eff > 0 requires chi < 4 tau (on every level; the fine
+  // level has the larger tau, so the coarse tau bounds both)
+  if (c.chi_max >= 4.0 * c.tau)
+    return set_error(LBM_EINVAL, "chi_max = %g >= 4 tau = %g (Sec. II.C stability bound)",
+                     c.chi_max, 4.0 * c.tau);
+  if (refined(c)) return validate_refinement(c);
+  return LBM_OK;
+}
+
+// device memory layout of one level: A, B, mask
+static void level_layout(Level& L, int lattice, int storage) {
+  const int q = lattice;
+  L.q = q;
+  L.pstride = pop_stride((uint64_t)L.N);
+  const size_t popbytes = align_up(L.pstride * storage_bytes(storage), 256);
+  L.buf_bytes = popbytes * q;
+  L.off_buf[0] = 0;
+  L.off_buf[1] = L.buf_bytes;
+  L.off_mask = 2 * L.buf_bytes;
+  L.bytes = align_up(L.off_mask + (size_t)L.N, 256);
+}
+
+void plan_layout(lbm_ctx* ctx) {
+  const lbm_config& c = ctx->cfg;
+  size_t off = 256;  // status words first
+  for (int l = 0; l < ctx->nlevels; ++l) {
+    Level& L = ctx->lv[l];
+    level_layout(L, c.lattice, c.storage);
+    L.base_off = off;
+    off += L.bytes;
+  }
+  off = plan_interface_layout(ctx, off);
+  ctx->total_bytes = off;
+}
+
+}  // namespace hrlbm
+
+using namespace hrlbm;
+
+extern "C" {
+
+void lbm_config_init(lbm_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(lbm_config);
+  cfg->lattice = LBM_D3Q19;
+  cfg->storage = LBM_F32;
+  cfg->nx = cfg->ny = cfg->nz = 64;
+  cfg->tau = 0.6;
+  cfg->rho0 = 1.0;
+  cfg->u_dir[0] = 1.0;
+  cfg->rho_ref = 1.0;
+}
+
+static int make_levels(lbm_ctx* ctx) {
+  const lbm_config& c = ctx->cfg;
+  ctx->nlevels = 1;
+  Level& L0 = ctx->lv[0];
+  L0.nx = c.nx;
+  L0.ny = c.ny;
+  L0.nz = c.nz;
+  L0.N = c.nx * c.ny * c.nz;
+  L0.tau = c.tau;
+  L0.level = 0;
+  for (int f = 0; f < 6; ++f) {
+    L0.face[f] = c.face_bc[f];
+    L0.sponge[f] = c.sponge_width[f];
+  }
+  L0.chi_max = c.chi_max;
+  if (refined(c)) return make_fine_level(ctx);
+  return LBM_OK;
+}
+
+size_t lbm_required_bytes(const lbm_config* cfg) {
+  if (validate(cfg) != LBM_OK) return 0;
+  lbm_ctx tmp;
+  tmp.cfg = *cfg;
+  if (make_levels(&tmp) != LBM_OK) return 0;
+  plan_layout(&tmp);
+  return tmp.total_bytes;
+}
+
+int lbm_create(const lbm_config* cfg, lbm_ctx** out) {
+  if (!out) return set_error(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc != LBM_OK) return rc;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+  if (cfg->device < 0 || cfg->device >= ndev)
+    return set_error(LBM_EINVAL, "device %d of %d", cfg->device, ndev);
+  lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+  if (!ctx) return set_error(LBM_ENOMEM, "host allocation");
+  ctx->cfg = *cfg;
+  ctx->stream = (hipStream_t)cfg->stream;
+  ctx->device = cfg->device;
+  inlet_velocity(ctx->cfg, ctx->uin);
+  rc = make_levels(ctx);
+  if (rc != LBM_OK) {
+    delete ctx;
+    return rc;
+  }
+  plan_layout(ctx);
+  ctx->block = cfg->block ? (int)cfg->block : 256;
+  if (ctx->block % 64 || ctx->block < 64 || ctx->block > 1024) {
+    delete ctx;
+    return set_error(LBM_EINVAL, "block %u: multiple of 64 in [64, 1024]", cfg->block);
+  }
+  *out = ctx;
+  return LBM_OK;
+}
+
+int lbm_bind_memory(lbm_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  if (ctx->mem) return set_error(LBM_ESTATE, "memory already set up (bind before lbm_init)");
+  if (!dev_ptr || ((uintptr_t)dev_ptr % 256))
+    return set_error(LBM_EINVAL, "buffer must be non-NULL and 256-byte aligned");
+  if (bytes < ctx->total_bytes)
+    return set_error(LBM_ENOMEM, "bound buffer has %zu bytes, need %zu", bytes, ctx->total_bytes);
+  ctx->mem = (char*)dev_ptr;
+  ctx->owns_mem = false;
+  assign_pointers(ctx);
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace hrlbm {
+
+void assign_pointers(lbm_ctx* ctx) {
+  ctx->status = (int*)ctx->mem;
+  for (int l = 0; l < ctx->nlevels; ++l) {
+    Level& L = ctx->lv[l];
+    char* b = ctx->mem + L.base_off;
+    L.buf[0] = b + L.off_buf[0];
+    L.buf[1] = b + L.off_buf[1];
+    L.mask = (uint8_t*)(b + L.off_mask);
+  }
+  assign_interface_pointers(ctx);
+}
+
+int ensure_device(const lbm_ctx* ctx) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  if (cur != ctx->device) {
+    e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+  }
+  return LBM_OK;
+}
+
+static int ensure_memory(lbm_ctx* ctx) {
+  if (ctx->mem) return LBM_OK;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, ctx->total_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(LBM_ENOMEM, "hipMalloc(%zu): %s", ctx->total_bytes, hipGetErrorString(e));
+  }
+  ctx->mem = (char*)p;
+  ctx->owns_mem = true;
+  assign_pointers(ctx);
+  return LBM_OK;
+}
+
+// Fill the sweep arguments of level l for one step producing time t_new.
+SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
+  const Level& L = ctx->lv[l];
+  const lbm_config& c = ctx->cfg;
+  SweepHost h{};
+  h.src = L.buf[src_buf];
+  h.dst = L.buf[src_buf ^ 1];
+  h.mask = L.has_mask ? L.mask : nullptr;
+  h.status = ctx->status;
+  h.nx = (uint32_t)L.nx;
+  h.ny = (uint32_t)L.ny;
+  h.nz = (uint32_t)L.nz;
+  h.pstride = L.pstride;
+  h.tau = L.tau;
+  h.rho0 = c.rho0;
+  h.chi_max = L.chi_max;
+  h.rho_ref = c.rho_ref;
+  for (int a = 0; a < 3; ++a) {
+    h.uref[a] = c.lattice == LBM_D2Q9 && a == 2 ? 0.0 : c.u_ref[a];
+    h.uin[a] = ctx->uin[a];
+  }
+  h.noise = c.inlet_noise;
+  bool general = L.has_mask || L.chi_max > 0;
+  for (int f = 0; f < 6; ++f) {
+    h.face[f] = L.face[f];
+    h.sponge[f] = L.sponge[f];
+    if (L.face[f] != LBM_PERIODIC) general = true;
+  }
+  h.seed = c.seed;
+  h.t_new = t_new;
+  h.level = L.level;
+  h.general = general;
+  return h;
+}
+
+int check_ready(const lbm_ctx* ctx) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  if (!ctx->initialised) return set_error(LBM_ESTATE, "lbm_init has not been called");
+  return LBM_OK;
+}
+
+// One eager sweep of level l.
+int sweep_level(lbm_ctx* ctx, int l, hipStream_t st) {
+  Level& L = ctx->lv[l];
+  SweepHost h = sweep_args(ctx, l, L.cur, (uint64_t)(L.t + 1));
+  hipError_t e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, ctx->block, st);
+  if (e != hipSuccess) return hip_error(e, "sweep launch");
+  L.cur ^= 1;
+  L.t += 1;
+  return LBM_OK;
+}
+
+// Enqueue n single-grid steps eagerly.
+static int step_eager(lbm_ctx* ctx, int64_t n, hipStream_t st) {
+  for (int64_t s = 0; s < n; ++s) {
+    int rc = ctx->nlevels > 1 ? refined_coarse_step(ctx, st) : sweep_level(ctx, 0, st);
+    if (rc != LBM_OK) return rc;
+    if (ctx->nlevels == 1) ctx->t += 1;
+  }
+  return LBM_OK;
+}
+
+// Replaying captured step sequences: a graph holds kGraphSteps steps from a
+// given buffer parity and time; inlet noise depends on the absolute time,
+// so graphs are keyed by (parity, t mod period) only when no cell draws
+// noise, and otherwise not used.
+static constexpr int64_t kGraphSteps = 32;
+
+static void drop_graphs(lbm_ctx* ctx) {
+  for (auto& kv : ctx->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  ctx->graphs.clear();
+}
+
+static bool graphs_allowed(const lbm_ctx* ctx) {
+  if (ctx->cfg.flags & LBM_NO_GRAPH) return false;
+  // time-dependent kernel arguments (inlet noise, refinement schedule
+  // parities) would be frozen into the graph
+  if (ctx->has_inlet && ctx->cfg.inlet_noise != 0.0) return false;
+  if (ctx->nlevels > 1) return false;
+  return true;
+}
+
+static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
+  Level& L = ctx->lv[0];
+  const int key = L.cur;
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (!ctx->capture_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_error(e, "hipStreamCreate");
+    }
+    GraphEntry g{};
+    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    int buf = L.cur;
+    for (int64_t s = 0; s < kGraphSteps; ++s) {
+      SweepHost h = sweep_args(ctx, 0, buf, (uint64_t)(L.t + 1 + s));
+      e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
+      if (e != hipSuccess) break;
+      buf ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (e != hipSuccess) return hip_error(e, "sweep launch during capture");
+    if (e2 != hipSuccess) return hip_error(e2, "hipStreamEndCapture");
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_error(e, "hipGraphInstantiate");
+    }
+    it = ctx->graphs.emplace(key, g).first;
+  }
+  for (int64_t k = 0; k < chunks; ++k) {
+    hipError_t e = hipGraphLaunch(it->second.exec, st);
+    if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  }
+  // kGraphSteps is even: the buffer parity is unchanged
+  L.t += chunks * kGraphSteps;
+  ctx->t += chunks * kGraphSteps;
+  return LBM_OK;
+}
+
+int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st) {
+  if (n < 0) return set_error(LBM_EINVAL, "negative step count");
+  if (graphs_allowed(ctx) && n >= 2 * kGraphSteps) {
+    const int64_t chunks = n / kGraphSteps;
+    int rc = step_graph(ctx, chunks, st);
+    if (rc != LBM_OK) return rc;
+    n -= chunks * kGraphSteps;
+  }
+  return step_eager(ctx, n, st);
+}
+
+}  // namespace hrlbm
+
+extern "C" {
+
+int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
+             const double* pi_neq, const uint8_t* mask) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  if (level < 0 || level >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  int rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  rc = ensure_memory(ctx);
+  if (rc != LBM_OK) return rc;
+  Level& L = ctx->lv[level];
+  hipError_t e;
+  if (!ctx->status_cleared) {
+    e = hipMemsetAsync(ctx->status, 0, 256, ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "hipMemsetAsync");
+    ctx->status_cleared = true;
+  }
+  InitArgs a{};
+  a.rho = rho;
+  a.u = u;
+  a.pineq = pi_neq;
+  a.mask_in = mask;
+  a.mask_out = L.mask;
+  a.dst0 = L.buf[0];
+  a.dst1 = L.buf[1];
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  a.omega1 = 1.0 - 1.0 / L.tau;
+  for (int k = 0; k < 3; ++k) a.uin[k] = ctx->uin[k];
+  e = launch_init(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "init launch");
+  L.has_mask = mask != nullptr;
+  if (mask) {
+    // inlet cells draw noise: note whether any exist (host scan of a copy)
+    std::vector<uint8_t> hm((size_t)L.N);
+    e = hipMemcpyAsync(hm.data(), mask, (size_t)L.N, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "mask copy");
+    for (uint8_t m : hm)
+      if (m == LBM_INLET) {
+        ctx->has_inlet = true;
+        break;
+      }
+    for (uint8_t m : hm)
+      if (m > LBM_INLET) return set_error(LBM_EINVAL, "mask value %u", (unsigned)m);
+  }
+  L.cur = 0;
+  L.t = 0;
+  L.initialised = true;
+  ctx->t = 0;
+  for (int l = 0; l < ctx->nlevels; ++l) ctx->lv[l].t = 0;
+  drop_graphs(ctx);
+  bool all = true;
+  for (int l = 0; l < ctx->nlevels; ++l) all = all && ctx->lv[l].initialised;
+  ctx->initialised = all;
+  if (all && ctx->nlevels > 1) return refined_after_init(ctx);
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int64_t n) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  return step_ctx(ctx, n, ctx->stream);
+}
+
+int lbm_sync(lbm_ctx* ctx) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  int rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  if (!ctx->mem) return LBM_OK;
+  int flag = 0;
+  e = hipMemcpy(&flag, ctx->status, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(e, "status copy");
+  if (flag) ctx->unstable = true;
+  if (ctx->unstable)
+    return set_error(LBM_EUNSTABLE, "non-finite or non-positive density seen");
+  return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* ctx) { return ctx ? ctx->t : -1; }
+
+int lbm_level_shape(const lbm_ctx* ctx, int level, int64_t* nx, int64_t* ny,
+                    int64_t* nz) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  if (level < 0 || level >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  const Level& L = ctx->lv[level];
+  if (nx) *nx = L.nx;
+  if (ny) *ny = L.ny;
+  if (nz) *nz = L.nz;
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* ctx, int level, double* rho_out, double* u_out) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  const Level& L = ctx->lv[level];
+  MomentArgs a{};
+  a.src = L.buf[L.cur];
+  a.mask = L.has_mask ? L.mask : nullptr;
+  a.rho_out = rho_out;
+  a.u_out = u_out;
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_moments(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "moments launch");
+  if (ctx->unstable) return set_error(LBM_EUNSTABLE, "non-finite or non-positive density seen");
+  return LBM_OK;
+}
+
+int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n, double* rho_out) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  if (n < 0 || (n > 0 && (!cells || !rho_out)))
+    return set_error(LBM_EINVAL, "probe arguments");
+  if (n == 0) return LBM_OK;
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  const Level& L = ctx->lv[level];
+  ProbeArgs a{};
+  a.src = L.buf[L.cur];
+  a.mask = L.has_mask ? L.mask : nullptr;
+  a.cells = cells;
+  a.rho_out = rho_out;
+  a.n = n;
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_probe(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)n, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "probe launch");
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx* ctx, int level, double* out) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels || !out)
+    return set_error(LBM_EINVAL, "level %d / output", level);
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  const Level& L = ctx->lv[level];
+  PopArgs a{};
+  a.native = L.buf[L.cur];
+  a.canon = out;
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_get_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "get_populations launch");
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels || !in)
+    return set_error(LBM_EINVAL, "level %d / input", level);
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  Level& L = ctx->lv[level];
+  PopArgs a{};
+  a.native = L.buf[L.cur];
+  // SOLID cells are never written by the sweep; keep both buffers equal
+  a.native2 = L.buf[L.cur ^ 1];
+  a.canon = const_cast<double*>(in);
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_set_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "set_populations launch");
+  if (ctx->nlevels > 1) return refined_after_set(ctx, level);
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return;
+  if (ensure_device(ctx) == LBM_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->owns_mem && ctx->mem) (void)hipFree(ctx->mem);
+  }
+  delete ctx;
+}
+
+int lbm_lattice_table(int lattice, int32_t* xi, double* w) {
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q27)
+    return set_error(LBM_EINVAL, "unknown lattice %d", lattice);
+  for (int i = 0; i < lattice; ++i) {
+    Dir d{};
+    double wi = 0;
+    switch (lattice) {
+      case 9: d = Lattice<9>::dir(i); wi = Lattice<9>::w(i); break;
+      case 19: d = Lattice<19>::dir(i); wi = Lattice<19>::w(i); break;
+      default: d = Lattice<27>::dir(i); wi = Lattice<27>::w(i); break;
+    }
+    if (xi) {
+      xi[3 * i] = d.x;
+      xi[3 * i + 1] = d.y;
+      xi[3 * i + 2] = d.z;
+    }
+    if (w) w[i] = wi;
+  }
+  return lattice;
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

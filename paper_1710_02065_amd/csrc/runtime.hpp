@@ -1,0 +1,93 @@
+// Context and level state shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "launch.hpp"
+
+namespace hrlbm {
+
+struct Level {
+  int level = 0;
+  int q = 0;
+  int64_t nx = 0, ny = 0, nz = 0, N = 0;
+  double tau = 0.6;
+  double chi_max = 0.0;
+  int32_t face[6] = {0, 0, 0, 0, 0, 0};
+  int32_t sponge[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t pstride = 0;
+  size_t buf_bytes = 0, bytes = 0, base_off = 0;
+  size_t off_buf[2] = {0, 0}, off_mask = 0;
+  void* buf[2] = {nullptr, nullptr};
+  uint8_t* mask = nullptr;
+  bool has_mask = false;
+  bool initialised = false;
+  int cur = 0;    // buffer holding the current state
+  int64_t t = 0;  // time index on this level
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct Refinement;  // two-level coupling state (refine.hip)
+
+}  // namespace hrlbm
+
+struct lbm_ctx {
+  lbm_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  int nlevels = 1;
+  hrlbm::Level lv[2];
+  double uin[3] = {0, 0, 0};
+  char* mem = nullptr;
+  bool owns_mem = false;
+  size_t total_bytes = 0;
+  int* status = nullptr;
+  bool status_cleared = false;
+  bool unstable = false;
+  bool initialised = false;
+  bool has_inlet = false;
+  int64_t t = 0;
+  int block = 256;
+  std::map<int, hrlbm::GraphEntry> graphs;
+  hrlbm::Refinement* ref = nullptr;
+  size_t ref_off = 0, ref_bytes = 0;
+  ~lbm_ctx();
+};
+
+namespace hrlbm {
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+int lattice_dim(int lattice);
+size_t storage_bytes(int storage);
+uint64_t pop_stride(uint64_t n);
+int validate(const lbm_config* cfg);
+void plan_layout(lbm_ctx* ctx);
+void assign_pointers(lbm_ctx* ctx);
+int ensure_device(const lbm_ctx* ctx);
+int check_ready(const lbm_ctx* ctx);
+SweepHost sweep_args(const lbm_ctx* ctx, int level, int src_buf, uint64_t t_new);
+int sweep_level(lbm_ctx* ctx, int level, hipStream_t st);
+int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st);
+
+// two-level refinement (refine.hip)
+int validate_refinement(const lbm_config& c);
+int make_fine_level(lbm_ctx* ctx);
+size_t plan_interface_layout(lbm_ctx* ctx, size_t off);
+void assign_interface_pointers(lbm_ctx* ctx);
+int refined_after_init(lbm_ctx* ctx);
+int refined_after_set(lbm_ctx* ctx, int level);
+int refined_coarse_step(lbm_ctx* ctx, hipStream_t st);
+void free_refinement(lbm_ctx* ctx);
+
+}  // namespace hrlbm

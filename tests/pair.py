@@ -1,0 +1,74 @@
+"""Helpers that run the same case through the GPU library and the oracle.
+
+A case is a dict of configuration keys shared by both sides (lattice q,
+shape, tau, rho0, ma, u_dir, face_bc, sponge_width, chi_max, rho_ref, u_ref,
+seed, inlet_noise) plus optional initial fields and a mask from
+paper_1710_02065_amd.workloads.
+"""
+import math
+import sys
+
+import numpy as np
+
+import oracle as O
+
+CS = math.sqrt(1.0 / 3.0)
+
+
+def normwise(a, ref):
+    """max |a - ref| / max |ref|"""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def inlet_velocity(case):
+    d = np.array(case.get("u_dir", (1.0, 0.0, 0.0)), dtype=float)
+    n = np.linalg.norm(d)
+    u = case.get("ma", 0.0) * CS * d / n if n > 0 else np.zeros(3)
+    if case["q"] == 9:
+        u[2] = 0.0
+    return tuple(u)
+
+
+def oracle_grid(case):
+    nx, ny, nz = case["shape"]
+    return O.Grid(case["q"], nx, ny, nz, tau=case.get("tau", 0.6), rho0=case.get("rho0", 1.0),
+                  u_in=inlet_velocity(case), face_bc=case.get("face_bc", (0,) * 6),
+                  sponge_width=case.get("sponge_width", (0,) * 6),
+                  chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
+                  u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
+                  inlet_noise=case.get("inlet_noise", 0.0), mask=case.get("mask"))
+
+
+def gpu_sim(case, storage="f64", **kw):
+    from paper_1710_02065_amd import lbm
+    args = dict(lattice=case["q"], shape=case["shape"], tau=case.get("tau", 0.6),
+                storage=storage, rho0=case.get("rho0", 1.0), ma=case.get("ma", 0.0),
+                u_dir=case.get("u_dir", (1.0, 0.0, 0.0)), face_bc=case.get("face_bc", (0,) * 6),
+                sponge_width=case.get("sponge_width", (0,) * 6),
+                chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
+                u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
+                inlet_noise=case.get("inlet_noise", 0.0))
+    args.update(kw)
+    return lbm.Simulation(**args)
+
+
+def log(msg):
+    """Name the case on stdout before each GPU step (flushed)."""
+    sys.stdout.write("[case] %s\n" % msg)
+    sys.stdout.flush()
+
+
+def run_both(case, steps, storage="f64", rho=None, u=None, pineq=None, **kw):
+    """Initialise both sides from the same fields and advance `steps`;
+    return (gpu populations, oracle populations, gpu sim, oracle grid)."""
+    log("%s q=%d shape=%s storage=%s steps=%d" % (case.get("name", "?"), case["q"],
+                                                  case["shape"], storage, steps))
+    sim = gpu_sim(case, storage, **kw)
+    sim.init(rho, u, pineq, case.get("mask"))
+    sim.step(steps)
+    gf = sim.populations().cpu().numpy()
+    sim.sync()
+    g = oracle_grid(case).init(rho, u, pineq).step(steps)
+    return gf, g.f, sim, g

@@ -1,0 +1,90 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/lbm.h declares, validates configurations, and reports the documented
+direction order."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1710_02065_amd import lbm
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "lbm.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 18
+    L = lbm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbm.EXPORTS) == names
+
+
+def test_config_struct_size_matches_binding():
+    cfg = lbm.lbm_config_init()
+    assert cfg.struct_size == C.sizeof(lbm.lbm_config)
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_direction_order_matches_oracle(q):
+    xi, w = lbm.lbm_lattice_table(q)
+    oxi, ow, _ = O.lattice(q)
+    np.testing.assert_array_equal(xi, oxi)
+    np.testing.assert_allclose(w, ow, rtol=0, atol=1e-17)
+
+
+def required(**kw):
+    return lbm.lbm_required_bytes(lbm.make_config(**kw))
+
+
+def test_required_bytes_counts_both_buffers():
+    n = required(lattice=19, shape=(64, 64, 64), storage="f32")
+    pop = 64 ** 3 * 4 * 19 * 2
+    assert pop <= n < pop * 1.01 + (1 << 20)
+    assert required(lattice=19, shape=(64, 64, 64), storage="f16s") < n * 0.6
+    assert required(lattice=9, shape=(128, 128, 1), storage="f64") >= 128 * 128 * 9 * 8 * 2
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=0.6, chi_max=2.4), "chi_max"),
+    (dict(ma=0.7), "Ma"),
+    (dict(lattice=15), "lattice"),
+    (dict(storage=7), "storage"),
+    (dict(lattice=9, shape=(8, 8, 2)), "nz"),
+    (dict(face_bc=(0, 1, 0, 0, 0, 0)), "periodic"),
+    (dict(shape=(2048, 2048, 1024)), "2^31"),
+    (dict(sponge_width=(100, 0, 0, 0, 0, 0)), "sponge"),
+])
+def test_invalid_configurations_rejected(bad, msg):
+    kw = dict(lattice=19, shape=(64, 64, 64))
+    kw.update(bad)
+    assert required(**kw) == 0
+    assert msg.lower() in lbm.lbm_last_error().lower()
+
+
+def test_high_mach_flag():
+    assert required(ma=0.7, flags=lbm.LBM_ALLOW_HIGH_MA) > 0
+
+
+def test_create_without_device_reports_error():
+    """On a machine without a GPU, create fails cleanly (no crash)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(lbm.make_config())
+    assert e.value.code in (lbm.LBM_EDEVICE, lbm.LBM_EINVAL)

@@ -1,0 +1,308 @@
+"""GPU (HIP, gfx950) against the FP64 oracle, through the C ABI.
+
+Bars: FP64 build within 1e-12 normwise (max |gpu - oracle| / max |oracle|)
+on every case; FP32 formats within 2e-6 and the FP16-shifted format within
+2e-4 of one oracle step taken from the GPU's own stored state (the error
+of one step's arithmetic plus one storage rounding, derived in the design
+notes); integer-valued results (step counters, masks, bitwise replays)
+exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1710_02065_amd import workloads as W
+from tests.pair import gpu_sim, log, normwise, oracle_grid, run_both
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+TOL = {"f32": 2e-6, "f32s": 2e-6, "f16s": 2e-4}
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dim(q):
+    return 2 if q == 9 else 3
+
+
+RAGGED = {9: (45, 37, 1), 19: (17, 13, 11), 27: (15, 12, 9)}
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_init_parity_f64(q):
+    shape = RAGGED[q]
+    rho, u, p = W.random_state(shape, seed=10 + q, d=dim(q))
+    case = dict(name="init", q=q, shape=shape, tau=0.57)
+    gf, of, _, _ = run_both(case, 0, "f64", rho, u, p)
+    assert normwise(gf, of) <= F64_TOL
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+@pytest.mark.parametrize("steps", [1, 7])
+def test_periodic_step_parity_f64(q, steps):
+    shape = RAGGED[q]
+    rho, u, p = W.random_state(shape, seed=20 + q, d=dim(q))
+    case = dict(name="periodic", q=q, shape=shape, tau=0.53)
+    gf, of, _, _ = run_both(case, steps, "f64", rho, u, p)
+    assert normwise(gf, of) <= F64_TOL
+
+
+@pytest.mark.parametrize("q,shape", [(9, (1, 1, 1)), (9, (1, 5, 1)), (9, (7, 1, 1)),
+                                     (19, (1, 1, 1)), (19, (2, 3, 1)), (27, (3, 1, 2))])
+def test_degenerate_shapes_f64(q, shape):
+    rho, u, p = W.random_state(shape, seed=30, d=dim(q))
+    case = dict(name="degenerate", q=q, shape=shape, tau=0.8)
+    gf, of, _, _ = run_both(case, 3, "f64", rho, u, p)
+    assert normwise(gf, of) <= F64_TOL
+
+
+def channel_case(q):
+    """Cylinder-in-channel stand-in: inlet column with noise, free-slip
+    sides, zero-gradient outflow, sponge on the outflow face, SOLID disc."""
+    if q == 9:
+        nx, ny, nz = 96, 48, 1
+        mask = W.cylinder_mask(nx, ny, 12, 30, 24)
+        fb = (2, 2, 1, 1, 0, 0)
+        sw = (0, 16, 0, 0, 0, 0)
+    else:
+        nx, ny, nz = 40, 18, 14
+        mask = W.cylinder_mask(nx, ny, 6, 12, 9)
+        mask = np.tile(mask, nz)
+        fb = (2, 2, 1, 1, 2, 2)
+        sw = (0, 10, 0, 0, 4, 4)
+    return dict(name="channel", q=q, shape=(nx, ny, nz), tau=0.56, ma=0.2, u_dir=(1, 0, 0),
+                face_bc=fb, sponge_width=sw, chi_max=0.3, rho_ref=1.0,
+                u_ref=(0.2 / math.sqrt(3), 0, 0), seed=5, inlet_noise=0.02, mask=mask)
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_boundary_rules_parity_f64(q):
+    case = channel_case(q)
+    shape = case["shape"]
+    U = case["ma"] / math.sqrt(3)
+    rho, u = W.uniform_perturbed(shape, U, (1, 0, 0), seed=3, rel_noise=1e-2, d=dim(q))
+    gf, of, sim, g = run_both(case, 25, "f64", rho, u)
+    assert normwise(gf, of) <= F64_TOL
+    r_g, u_g = sim.moments()
+    r_o, u_o = g.moments()
+    assert normwise(r_g.cpu().numpy(), r_o) <= F64_TOL
+    assert normwise(u_g.cpu().numpy(), u_o) <= F64_TOL
+
+
+def test_closed_box_and_jet_inlet_parity_f64():
+    shape = (20, 18, 16)
+    mask = W.closed_box_mask(*shape)
+    mask[W.jet_inlet_mask(*shape, D=6) == W.INLET] = W.INLET
+    rho, u, p = W.random_state(shape, seed=4, d=3, u_amp=0.02)
+    case = dict(name="box+jet", q=27, shape=shape, tau=0.51, ma=0.3, seed=11,
+                inlet_noise=0.02, mask=mask, face_bc=(2, 2, 1, 1, 2, 2),
+                sponge_width=(0, 6, 3, 3, 3, 3), chi_max=0.2)
+    gf, of, _, _ = run_both(case, 15, "f64", rho, u, p)
+    assert normwise(gf, of) <= F64_TOL
+
+
+def test_taylor_green_config_f64():
+    """D2Q9 128^2 periodic, FP64, tau 0.6, U = 0.05, 1000 steps."""
+    n, U = 128, 0.05
+    rho, u, _ = W.taylor_green_2d(n, U)
+    case = dict(name="tg128", q=9, shape=(n, n, 1), tau=0.6)
+    gf, of, sim, g = run_both(case, 1000, "f64", rho, u)
+    assert normwise(gf, of) <= F64_TOL
+    r_g, u_g = sim.moments()
+    r_o, u_o = g.moments()
+    assert normwise(u_g.cpu().numpy(), u_o) <= F64_TOL
+    assert sim.time == 1000
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+@pytest.mark.parametrize("storage", ["f32", "f32s", "f16s"])
+def test_low_precision_single_step(q, storage):
+    """One step in FP32 arithmetic from the GPU's stored state against one
+    oracle step from the same (exactly converted) state."""
+    shape = RAGGED[q]
+    rho, u, p = W.random_state(shape, seed=40 + q, d=dim(q))
+    case = channel_case(q) if q == 19 else dict(name="lowprec", q=q, shape=shape, tau=0.52)
+    if q == 19:
+        shape = case["shape"]
+        rho, u, p = W.random_state(shape, seed=40 + q, d=3)
+    log("lowprec q=%d storage=%s" % (q, storage))
+    sim = gpu_sim(case, storage)
+    sim.init(rho, u, p, case.get("mask"))
+    sim.step(2)
+    f0 = sim.populations().cpu().numpy()
+    sim.step(1)
+    f1 = sim.populations().cpu().numpy()
+    sim.sync()
+    g = oracle_grid(case)
+    g.set_populations(f0)
+    g.t = 2
+    g.step(1)
+    assert normwise(f1, g.f) <= TOL[storage]
+
+
+def test_moments_and_probe_match_oracle():
+    case = channel_case(9)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=8, rel_noise=0.05, d=2)
+    _, _, sim, g = run_both(case, 10, "f64", rho, u)
+    r_o, _ = g.moments()
+    cells = np.array([0, 5, 100, 2000, 4607], dtype=np.int64)
+    pr = sim.probe(cells).cpu().numpy()
+    np.testing.assert_allclose(pr, r_o[cells], rtol=1e-13, atol=0)
+
+
+def test_checkpoint_resume_bitwise():
+    case = dict(name="resume", q=19, shape=(20, 16, 12), tau=0.55, face_bc=(2, 2, 1, 1, 0, 0),
+                sponge_width=(0, 5, 0, 0, 0, 0), chi_max=0.3)
+    rho, u, p = W.random_state(case["shape"], seed=9, d=3)
+    for storage in ("f32", "f16s", "f64"):
+        log("resume storage=%s" % storage)
+        a = gpu_sim(case, storage).init(rho, u, p).step(20)
+        fa = a.populations().cpu().numpy()
+        b = gpu_sim(case, storage).init(rho, u, p).step(10)
+        fb = b.populations()
+        c = gpu_sim(case, storage).init(rho, u, p)
+        c.set_populations(fb)
+        c.step(10)
+        fc = c.populations().cpu().numpy()
+        np.testing.assert_array_equal(fa, fc)
+
+
+def test_run_to_run_bitwise_deterministic():
+    case = channel_case(9)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=8, rel_noise=0.05, d=2)
+    outs = []
+    for _ in range(2):
+        s = gpu_sim(case, "f32").init(rho, u, None, case["mask"]).step(50)
+        outs.append(s.populations().cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_graph_replay_matches_eager(storage):
+    from paper_1710_02065_amd import lbm
+    case = dict(name="graph", q=19, shape=(24, 20, 16), tau=0.55)
+    rho, u, p = W.random_state(case["shape"], seed=12, d=3)
+    log("graph storage=%s" % storage)
+    a = gpu_sim(case, storage).init(rho, u, p)
+    b = gpu_sim(case, storage, flags=lbm.LBM_NO_GRAPH).init(rho, u, p)
+    for n in (200, 70, 64, 3, 130):
+        a.step(n)
+        b.step(n)
+        fa = a.populations().cpu().numpy()
+        fb = b.populations().cpu().numpy()
+        np.testing.assert_array_equal(fa, fb)
+    assert a.time == b.time == 467
+
+
+@pytest.mark.parametrize("bad", ["negative", "nan"])
+def test_watchdog_reports_instability(bad):
+    """A cell whose pulled density is non-positive or not finite sets the
+    sticky flag; the next sync reports LBM_EUNSTABLE.  (A mildly negative
+    initial density is smoothed by streaming: the pulled density of that
+    cell is 1 - 4/9 * 1.5 > 0, so the forcing is strong.)"""
+    from paper_1710_02065_amd import lbm
+    case = dict(name="unstable-" + bad, q=9, shape=(16, 16, 1), tau=0.6)
+    rho = np.ones(256)
+    u = np.zeros((3, 256))
+    if bad == "negative":
+        rho[37] = -100.0
+    else:
+        u[0, 37] = np.nan
+    s = gpu_sim(case, "f32").init(rho, u)
+    s.sync()
+    s.step(2)
+    with pytest.raises(lbm.LbmError) as e:
+        s.sync()
+    assert e.value.code == lbm.LBM_EUNSTABLE
+    with pytest.raises(lbm.LbmError):  # sticky
+        s.sync()
+
+
+def test_step_batch_equals_solo():
+    from paper_1710_02065_amd import lbm
+    cases = [dict(name="b0", q=9, shape=(64, 48, 1), tau=0.6),
+             dict(name="b1", q=9, shape=(37, 91, 1), tau=0.7, face_bc=(2, 2, 1, 1, 0, 0),
+                  sponge_width=(0, 8, 0, 0, 0, 0), chi_max=0.2),
+             dict(name="b2", q=9, shape=(128, 30, 1), tau=0.52)]
+    steps = [40, 13, 77]
+    fields = [W.random_state(c["shape"], seed=50 + k, d=2) for k, c in enumerate(cases)]
+    for storage in ("f32", "f16s"):
+        log("batch storage=%s" % storage)
+        solo = []
+        for c, f, n in zip(cases, fields, steps):
+            solo.append(gpu_sim(c, storage).init(*f).step(n).populations().cpu().numpy())
+        sims = [gpu_sim(c, storage).init(*f) for c, f in zip(cases, fields)]
+        lbm.lbm_step_batch([s.ctx for s in sims], steps)
+        for s, ref, n in zip(sims, solo, steps):
+            np.testing.assert_array_equal(s.populations().cpu().numpy(), ref)
+            assert s.time == n
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_full_size_d3q19_sampled_parity(storage):
+    """D3Q19 256^3 periodic, Taylor-Green + acoustic pulse, in the launch
+    configuration the benchmark times.  After two GPU steps, a 24^3 block
+    (plus its one-cell halo) of the stored state is stepped once by the
+    oracle and compared with the GPU's third step on the block interior."""
+    n = 256
+    U = 0.1 / math.sqrt(3)
+    rho, u = W.taylor_green_3d(n, U, pulse_amp=1e-3, pulse_sigma=8.0)
+    case = dict(name="c3", q=19, shape=(n, n, n), tau=0.52)
+    log("full-size D3Q19 256^3 storage=%s" % storage)
+    sim = gpu_sim(case, storage).init(rho, u)
+    del rho, u
+    sim.step(2)
+    f0 = sim.populations()
+    lo = np.array([100, 117, 30])  # block origin (x, y, z) incl. halo
+    B = 26
+    idx = ((np.arange(lo[2], lo[2] + B)[:, None, None] * n
+            + np.arange(lo[1], lo[1] + B)[None, :, None]) * n
+           + np.arange(lo[0], lo[0] + B)[None, None, :]).ravel()
+    tidx = torch.from_numpy(idx).to(f0.device)
+    blk0 = f0[:, tidx].cpu().numpy()
+    del f0
+    sim.step(1)
+    f1 = sim.populations()
+    blk1 = f1[:, tidx].cpu().numpy()
+    del f1
+    sim.sync()
+    g = oracle_grid(dict(q=19, shape=(B, B, B), tau=0.52))
+    g.set_populations(blk0)
+    g.step(1)
+    inner = np.zeros((B, B, B), dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    inner = inner.ravel()
+    assert normwise(blk1[:, inner], g.f[:, inner]) <= TOL[storage]
+
+
+def test_full_size_channel_one_step():
+    """D2Q9 2048x1024 cylinder channel (D = 100 at (400, 512), inlet column,
+    free-slip sides, outflow with a 128-column sponge), FP32: one oracle
+    step from the GPU's stored state over the whole grid."""
+    nx, ny, D = 2048, 1024, 100
+    U = 0.2 / math.sqrt(3)
+    tau = 0.5 + 3 * U * D / 150
+    mask = W.cylinder_mask(nx, ny, D, 400, 512)
+    case = dict(name="c2", q=9, shape=(nx, ny, 1), tau=tau, ma=0.2, face_bc=(2, 2, 1, 1, 0, 0),
+                sponge_width=(0, 128, 0, 0, 0, 0), chi_max=0.2, rho_ref=1.0,
+                u_ref=(U, 0, 0), seed=2, mask=mask)
+    rho, u = W.uniform_perturbed((nx, ny, 1), U, (1, 0, 0), seed=2, rel_noise=1e-4, d=2)
+    log("full-size D2Q9 2048x1024 channel f32")
+    sim = gpu_sim(case, "f32").init(rho, u, None, mask)
+    sim.step(5)
+    f0 = sim.populations().cpu().numpy()
+    sim.step(1)
+    f1 = sim.populations().cpu().numpy()
+    sim.sync()
+    g = oracle_grid(case)
+    g.set_populations(f0)
+    g.t = 5
+    g.step(1)
+    assert normwise(f1, g.f) <= TOL["f32"]

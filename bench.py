@@ -44,14 +44,18 @@ def kernel_hash():
 def measured_traffic(name):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % name)
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as f:
-        d = json.load(f)
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("bytes_per_launch")
+    return int(d["bytes_per_launch"])
 
 
 def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0):
@@ -161,7 +165,7 @@ def main():
     bytes_lup = 2 * 19 * 4
     per_launch_s = ms32 / 1e3 / args.steps
     achieved = bytes_lup * N / per_launch_s / 1e9
-    traffic = measured_traffic("k_sweep_d3q19_f32_256")
+    traffic = measured_traffic("k_sweep_d3q19_f32_256") if n == 256 else None
 
     variants = {}
     precision = {}

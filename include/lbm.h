@@ -169,6 +169,11 @@ int lbm_sync(lbm_ctx* ctx);
 /* Steps completed (coarse time index). */
 int64_t lbm_time(const lbm_ctx* ctx);
 
+/* Cell updates one coarse step performs: all cells of an unrefined grid; on
+ * a refined context the swept coarse cells plus twice the swept fine cells
+ * (two fine substeps, eq. convective).  Used to report MLUPS. */
+int64_t lbm_updates_per_step(const lbm_ctx* ctx);
+
 /* Grid shape of a level. */
 int lbm_level_shape(const lbm_ctx* ctx, int level, int64_t* nx, int64_t* ny,
                     int64_t* nz);

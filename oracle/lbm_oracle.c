@@ -266,7 +266,8 @@ void ora_noneq(int lattice, const double* u, const double* a2packed,
 /* ------------------------------------------------------------------------ */
 static void ora_collide_cell(const ora_lattice* L, const double* f, double tau,
                              double chi, double rho_ref, const double* u_ref,
-                             double* post, double* rho_star, double* u_star) {
+                             double* post, double* rho_star, double* u_star,
+                             double* a2_out) {
   const double cs2 = ORA_CS2;
   double rho = 0.0, j[3] = {0, 0, 0}, Pi[3][3] = {{0}};
   double rs, js[3], u[3], a2[3][3];
@@ -308,13 +309,21 @@ static void ora_collide_cell(const ora_lattice* L, const double* f, double tau,
   if (rho_star) *rho_star = rs;
   if (u_star)
     for (a = 0; a < 3; ++a) u_star[a] = u[a];
+  if (a2_out) { /* packed (xx, yy, zz, xy, xz, yz) */
+    a2_out[0] = a2[0][0];
+    a2_out[1] = a2[1][1];
+    a2_out[2] = a2[2][2];
+    a2_out[3] = a2[0][1];
+    a2_out[4] = a2[0][2];
+    a2_out[5] = a2[1][2];
+  }
 }
 
 void ora_collide(int lattice, const double* f, double tau, double chi,
                  double rho_ref, const double* u_ref, double* post) {
   ora_lattice L;
   if (ora_make_lattice(lattice, &L)) return;
-  ora_collide_cell(&L, f, tau, chi, rho_ref, u_ref, post, NULL, NULL);
+  ora_collide_cell(&L, f, tau, chi, rho_ref, u_ref, post, NULL, NULL, NULL);
 }
 
 /* Standard LBM-BGK collision, eq. (standardLB) with the second-order
@@ -509,9 +518,13 @@ void ora_init(const ora_grid* g, const double* rho, const double* u,
 }
 
 /* Full update of the post-collision field from time t_new - 1 to t_new.
- * mask may be NULL (all fluid).  SOLID cells are copied unchanged. */
-void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
-              double* fout, int64_t t_new) {
+ * mask may be NULL (all fluid).  SOLID cells, and cells with skip[c] != 0
+ * (skip may be NULL), are copied unchanged.  When rho_out / u_out / a2_out
+ * are given, they receive the pre-collision moments rho*, u and a2_neq of
+ * every collided cell (untouched elsewhere). */
+void ora_step_ex(const ora_grid* g, const uint8_t* mask, const uint8_t* skip,
+                 const double* fin, double* fout, int64_t t_new,
+                 double* rho_out, double* u_out, double* a2_out) {
   ora_lattice L;
   int64_t N = g->nx * g->ny * g->nz, row;
   if (ora_make_lattice(g->lattice, &L)) return;
@@ -523,7 +536,7 @@ void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
         uint8_t m = mask ? mask[c] : ORA_FLUID;
         double f[27], post[27];
         int i;
-        if (m == ORA_SOLID) {
+        if (m == ORA_SOLID || (skip && skip[c])) {
           for (i = 0; i < L.q; ++i)
             fout[(int64_t)i * N + c] = fin[(int64_t)i * N + c];
           continue;
@@ -535,14 +548,26 @@ void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
           ora_feq(&L, g->rho0, uin, post);
         } else {
           double chi = ora_sponge_chi(g, x, y, z);
+          double rs, us[3], a2p[6];
+          int a;
           for (i = 0; i < L.q; ++i)
             f[i] = ora_pull(g, &L, mask, fin, x, y, z, i);
           ora_collide_cell(&L, f, g->tau, chi, g->rho_ref, g->u_ref, post,
-                           NULL, NULL);
+                           &rs, us, a2p);
+          if (rho_out) rho_out[c] = rs;
+          if (u_out)
+            for (a = 0; a < 3; ++a) u_out[(int64_t)a * N + c] = us[a];
+          if (a2_out)
+            for (a = 0; a < 6; ++a) a2_out[(int64_t)a * N + c] = a2p[a];
         }
         for (i = 0; i < L.q; ++i) fout[(int64_t)i * N + c] = post[i];
     }
   }
+}
+
+void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
+              double* fout, int64_t t_new) {
+  ora_step_ex(g, mask, NULL, fin, fout, t_new, NULL, NULL, NULL);
 }
 
 /* Density and velocity of the stored post-collision state at each cell:
@@ -574,3 +599,185 @@ void ora_moments(const ora_grid* g, const uint8_t* mask, const double* f,
 }
 
 int ora_sizeof_grid(void) { return (int)sizeof(ora_grid); }
+
+/* ------------------------------------------------------------------------ */
+/* Two-level 2:1 multi-domain refinement (Sec. II.B).                        */
+/*                                                                           */
+/* Layout (the paper's Fig. 1 is not available; this is the reading used):   */
+/* the fine grid covers the closed coarse-node box [lo, hi] with spacing 1/2 */
+/* (eq. convective: dx_f = dx_c / 2, dt_f = dt_c / 2), so fine node k sits   */
+/* at coarse coordinate lo + k/2 and an axis has 2 (hi - lo) + 1 fine nodes. */
+/*   RING:    fine nodes on the outer shell; rebuilt from coarse data.       */
+/*   IMPORT:  coarse nodes on the shell of [lo+1, hi-1]; rebuilt from fine   */
+/*            data.                                                          */
+/*   COVERED: coarse nodes strictly inside [lo+1, hi-1]; not updated.        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  ora_grid c; /* coarse grid (level 0) */
+  ora_grid f; /* fine grid (level 1) */
+  int64_t lo[3], hi[3];
+} ora_refined;
+
+enum { ORA_NORMAL = 0, ORA_IMPORT = 1, ORA_COVERED = 2 };
+
+int ora_sizeof_refined(void) { return (int)sizeof(ora_refined); }
+
+/* crole [Nc]: ORA_NORMAL / ORA_IMPORT / ORA_COVERED; fring [Nf]: 1 on RING */
+void ora_ref_roles(const ora_refined* R, uint8_t* crole, uint8_t* fring) {
+  const ora_grid* c = &R->c;
+  const ora_grid* f = &R->f;
+  int d = c->lattice == 9 ? 2 : 3;
+  int64_t x, y, z;
+  for (z = 0; z < c->nz; ++z)
+    for (y = 0; y < c->ny; ++y)
+      for (x = 0; x < c->nx; ++x) {
+        int64_t p[3] = {x, y, z};
+        int inside = 1, deep = 1, a;
+        for (a = 0; a < d; ++a) {
+          if (p[a] < R->lo[a] + 1 || p[a] > R->hi[a] - 1) inside = 0;
+          if (p[a] < R->lo[a] + 2 || p[a] > R->hi[a] - 2) deep = 0;
+        }
+        crole[ora_cell(c, x, y, z)] =
+            !inside ? ORA_NORMAL : (deep ? ORA_COVERED : ORA_IMPORT);
+      }
+  for (z = 0; z < f->nz; ++z)
+    for (y = 0; y < f->ny; ++y)
+      for (x = 0; x < f->nx; ++x) {
+        int ring = (x == 0 || x == f->nx - 1 || y == 0 || y == f->ny - 1);
+        if (d == 3) ring = ring || z == 0 || z == f->nz - 1;
+        fring[ora_cell(f, x, y, z)] = (uint8_t)ring;
+      }
+}
+
+/* Interpolation points along one axis for fine index k: the coincident
+ * coarse node, or for a midpoint the local cubic (-1, 9, 9, -1)/16 over the
+ * four nearest coarse nodes (Sec. II.B: at least cubic interpolation keeps
+ * second order).  Returns the number of points. */
+static int ora_axis_stencil(int64_t lo, int64_t k, int64_t n, int periodic,
+                            int64_t* idx, double* wts) {
+  if (k % 2 == 0) {
+    idx[0] = lo + k / 2;
+    wts[0] = 1.0;
+    return 1;
+  } else {
+    const double w4[4] = {-1.0 / 16, 9.0 / 16, 9.0 / 16, -1.0 / 16};
+    int64_t j = lo + (k - 1) / 2;
+    int m;
+    for (m = 0; m < 4; ++m) {
+      int64_t s = j - 1 + m;
+      if (periodic) s = (s % n + n) % n;
+      idx[m] = s;
+      wts[m] = w4[m];
+    }
+    return 4;
+  }
+}
+
+/* Post-collision state of every RING node (eq. couplingFC): interpolated
+ * rho~, u~ and Pi~_neq from the coarse pre-collision moments, blended in
+ * time as wa * (level a) + wb * (level b) (linear interpolation in time,
+ * Sec. II.B), then
+ *   f = f^{eqH}(rho~, u~) + (1 - 1/tau_f) f^{neqH}(alpha_cf Pi~_neq, u~)
+ * with alpha_cf = tau_f / (2 tau_c): the non-equilibrium stress scales
+ * with tau * dt, the Chapman-Enskog leading order the paper invokes. */
+void ora_ref_fill_ring(const ora_refined* R, const uint8_t* fring,
+                       const double* rho_a, const double* u_a,
+                       const double* a2_a, double wa, const double* rho_b,
+                       const double* u_b, const double* a2_b, double wb,
+                       double* ffine) {
+  const ora_grid* c = &R->c;
+  const ora_grid* f = &R->f;
+  ora_lattice L;
+  int64_t Nc = c->nx * c->ny * c->nz, Nf = f->nx * f->ny * f->nz, cf;
+  const double alpha_cf = f->tau / (2.0 * c->tau);
+  int d;
+  if (ora_make_lattice(c->lattice, &L)) return;
+  d = L.d;
+#pragma omp parallel for schedule(static)
+  for (cf = 0; cf < Nf; ++cf) {
+    int64_t k[3], ix[3][4], cdims[3] = {c->nx, c->ny, c->nz};
+    double wx[3][4], rho = 0, u[3] = {0, 0, 0}, p6[6] = {0, 0, 0, 0, 0, 0};
+    double a2[3][3], E[27], Nq[27];
+    int np[3], a, i, m0, m1, m2;
+    if (!fring[cf]) continue;
+    k[0] = cf % f->nx;
+    k[1] = (cf / f->nx) % f->ny;
+    k[2] = cf / (f->nx * f->ny);
+    for (a = 0; a < 3; ++a) {
+      if (a < d)
+        np[a] = ora_axis_stencil(R->lo[a], k[a], cdims[a],
+                                 c->face_bc[2 * a] == ORA_PERIODIC, ix[a], wx[a]);
+      else {
+        np[a] = 1;
+        ix[a][0] = 0;
+        wx[a][0] = 1.0;
+      }
+    }
+    for (m2 = 0; m2 < np[2]; ++m2)
+      for (m1 = 0; m1 < np[1]; ++m1)
+        for (m0 = 0; m0 < np[0]; ++m0) {
+          int64_t cc = ora_cell(c, ix[0][m0], ix[1][m1], ix[2][m2]);
+          double w = wx[0][m0] * wx[1][m1] * wx[2][m2];
+          rho += w * (wa * rho_a[cc] + wb * rho_b[cc]);
+          for (a = 0; a < 3; ++a)
+            u[a] += w * (wa * u_a[a * Nc + cc] + wb * u_b[a * Nc + cc]);
+          for (a = 0; a < 6; ++a)
+            p6[a] += w * (wa * a2_a[a * Nc + cc] + wb * a2_b[a * Nc + cc]);
+        }
+    for (a = 0; a < 6; ++a) p6[a] *= alpha_cf;
+    if (d == 2) u[2] = p6[2] = p6[4] = p6[5] = 0.0;
+    ora_unpack6(p6, a2);
+    ora_feq(&L, rho, u, E);
+    ora_fneq(&L, u, a2, Nq);
+    for (i = 0; i < L.q; ++i)
+      ffine[(int64_t)i * Nf + cf] = E[i] + (1.0 - 1.0 / f->tau) * Nq[i];
+  }
+}
+
+/* Post-collision state of every IMPORT coarse node (eq. couplingCF): rho, u
+ * copied from the coincident fine node; Pi_neq low-pass filtered with the
+ * tensor weights (1/4, 1/2, 1/4) over the 3^D fine neighbours and rescaled
+ * by alpha_fc = 2 tau_c / tau_f (only f_neq is filtered: Sec. II.B);
+ *   f = f^{eqH}(rho, u) + (1 - 1/tau_c) f^{neqH}(alpha_fc Pi_neq, u).
+ * rho_f, u_f, a2_f: fine pre-collision moments at the same time level. */
+void ora_ref_import(const ora_refined* R, const uint8_t* crole,
+                    const double* rho_f, const double* u_f, const double* a2_f,
+                    double* fcoarse) {
+  const ora_grid* c = &R->c;
+  const ora_grid* f = &R->f;
+  ora_lattice L;
+  int64_t Nc = c->nx * c->ny * c->nz, Nf = f->nx * f->ny * f->nz, cc;
+  const double alpha_fc = 2.0 * c->tau / f->tau;
+  const double w1[3] = {0.25, 0.5, 0.25};
+  if (ora_make_lattice(c->lattice, &L)) return;
+#pragma omp parallel for schedule(static)
+  for (cc = 0; cc < Nc; ++cc) {
+    int64_t p[3], kc[3];
+    double p6[6] = {0, 0, 0, 0, 0, 0}, u[3], rho, a2[3][3], E[27], Nq[27];
+    int a, i, o0, o1, o2, oz = L.d == 3 ? 1 : 0;
+    int64_t center;
+    if (crole[cc] != ORA_IMPORT) continue;
+    p[0] = cc % c->nx;
+    p[1] = (cc / c->nx) % c->ny;
+    p[2] = cc / (c->nx * c->ny);
+    for (a = 0; a < 3; ++a) kc[a] = a < L.d ? 2 * (p[a] - R->lo[a]) : 0;
+    center = ora_cell(f, kc[0], kc[1], kc[2]);
+    rho = rho_f[center];
+    for (a = 0; a < 3; ++a) u[a] = u_f[a * Nf + center];
+    for (o2 = -oz; o2 <= oz; ++o2)
+      for (o1 = -1; o1 <= 1; ++o1)
+        for (o0 = -1; o0 <= 1; ++o0) {
+          int64_t fc = ora_cell(f, kc[0] + o0, kc[1] + o1, kc[2] + o2);
+          double w = w1[o0 + 1] * w1[o1 + 1] * (oz ? w1[o2 + 1] : 1.0);
+          for (a = 0; a < 6; ++a) p6[a] += w * a2_f[a * Nf + fc];
+        }
+    for (a = 0; a < 6; ++a) p6[a] *= alpha_fc;
+    if (L.d == 2) u[2] = p6[2] = p6[4] = p6[5] = 0.0;
+    ora_unpack6(p6, a2);
+    ora_feq(&L, rho, u, E);
+    ora_fneq(&L, u, a2, Nq);
+    for (i = 0; i < L.q; ++i)
+      fcoarse[(int64_t)i * Nc + cc] = E[i] + (1.0 - 1.0 / c->tau) * Nq[i];
+  }
+}

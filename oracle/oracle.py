@@ -39,8 +39,16 @@ def lib():
         L.ora_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, C.c_int64]
         L.ora_moments.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp]
         L.ora_sizeof_grid.restype = C.c_int
+        L.ora_step_ex.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp, dp, C.c_int64,
+                                  dp, dp, dp]
+        L.ora_sizeof_refined.restype = C.c_int
+        L.ora_ref_roles.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_ref_fill_ring.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, C.c_double,
+                                        dp, dp, dp, C.c_double, dp]
+        L.ora_ref_import.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, dp]
         _lib = L
         assert L.ora_sizeof_grid() == C.sizeof(OraGrid), "ora_grid layout mismatch"
+        assert L.ora_sizeof_refined() == C.sizeof(OraRefined), "ora_refined layout mismatch"
     return _lib
 
 
@@ -185,3 +193,115 @@ class Grid:
 
     def chi(self, x, y, z=0):
         return lib().ora_sponge_chi(C.byref(self.g), x, y, z)
+
+
+class OraRefined(C.Structure):
+    _fields_ = [("c", OraGrid), ("f", OraGrid), ("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3)]
+
+
+NORMAL, IMPORT, COVERED = 0, 1, 2
+
+
+def _u8p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class RefinedGrid:
+    """Two-level 2:1 refinement (Sec. II.B) advanced by the oracle.
+
+    The fine grid covers the closed coarse-node box [lo, hi] with half the
+    spacing and half the time step (eq. convective); tau_f = (4 tau_c - 1)/2
+    so the physical viscosity is the same on both levels.  One coarse step:
+      1. coarse sweep of NORMAL nodes (records coarse pre-collision moments
+         M_c(t+1));
+      2. fine sweep of the non-RING nodes (fine time 2t -> 2t+1);
+      3. RING <- cubic-in-space interpolation of (M_c(t) + M_c(t+1)) / 2;
+      4. fine sweep (2t+1 -> 2t+2), recording fine pre-collision moments;
+      5. RING <- interpolation of M_c(t+1);
+      6. IMPORT coarse nodes <- filtered fine moments.
+    """
+
+    def __init__(self, q, nx, ny, nz, lo, hi, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
+                 face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0, rho_ref=1.0,
+                 u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0, mask=None, fine_mask=None):
+        d = 2 if q == 9 else 3
+        lo = list(lo) + [0] * (3 - len(lo))
+        hi = list(hi) + [0] * (3 - len(hi))
+        fshape = [2 * (hi[a] - lo[a]) + 1 if a < d else 1 for a in range(3)]
+        tau_f = (4.0 * tau - 1.0) / 2.0
+        self.coarse = Grid(q, nx, ny, nz, tau=tau, rho0=rho0, u_in=u_in, face_bc=face_bc,
+                           sponge_width=sponge_width, chi_max=chi_max, rho_ref=rho_ref,
+                           u_ref=u_ref, seed=seed, inlet_noise=inlet_noise, mask=mask, level=0)
+        self.fine = Grid(q, *fshape, tau=tau_f, rho0=rho0, u_in=u_in,
+                         face_bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW,
+                                  OUTFLOW if d == 3 else PERIODIC, OUTFLOW if d == 3 else PERIODIC),
+                         seed=seed, inlet_noise=inlet_noise, mask=fine_mask, level=1)
+        R = OraRefined()
+        R.c = self.coarse.g
+        R.f = self.fine.g
+        R.lo[:] = lo
+        R.hi[:] = hi
+        self.R = R
+        self.q, self.d = q, d
+        self.crole = np.zeros(self.coarse.N, dtype=np.uint8)
+        self.fring = np.zeros(self.fine.N, dtype=np.uint8)
+        lib().ora_ref_roles(C.byref(R), _u8p(self.crole), _u8p(self.fring))
+        self.cskip = (self.crole != NORMAL).astype(np.uint8)
+        Nc, Nf = self.coarse.N, self.fine.N
+        self.M_prev = [np.zeros(Nc), np.zeros((3, Nc)), np.zeros((6, Nc))]
+        self.M_next = None
+        self.mf = [np.zeros(Nf), np.zeros((3, Nf)), np.zeros((6, Nf))]
+        self.inited = [False, False]
+        self.t = 0
+
+    def init(self, level, rho=None, u=None, pineq=None):
+        g = self.coarse if level == 0 else self.fine
+        g.init(rho, u, pineq)
+        if level == 0:
+            # coarse moments at t = 0 are the initial fields
+            N = g.N
+            self.M_prev[0][:] = g.g.rho0 if rho is None else np.asarray(rho, dtype=float).reshape(N)
+            if u is None:
+                self.M_prev[1][:] = np.array(g.g.u_in[:])[:, None]
+            else:
+                uu = np.asarray(u, dtype=float).reshape(-1, N)
+                self.M_prev[1][:] = 0.0
+                self.M_prev[1][: uu.shape[0]] = uu
+            self.M_prev[2][:] = 0.0 if pineq is None else np.asarray(pineq, dtype=float).reshape(6, N)
+            if self.d == 2:
+                self.M_prev[1][2] = 0.0
+                self.M_prev[2][[2, 4, 5]] = 0.0
+        self.inited[level] = True
+        if all(self.inited):
+            self.M_next = [a.copy() for a in self.M_prev]
+            self._fill_ring(self.M_prev, 1.0, self.M_prev, 0.0)
+            self.t = 0
+            self.coarse.t = 0
+            self.fine.t = 0
+        return self
+
+    def _fill_ring(self, Ma, wa, Mb, wb):
+        lib().ora_ref_fill_ring(C.byref(self.R), _u8p(self.fring), _dp(Ma[0]), _dp(Ma[1]),
+                                _dp(Ma[2]), wa, _dp(Mb[0]), _dp(Mb[1]), _dp(Mb[2]), wb,
+                                _dp(self.fine.f))
+
+    def _sweep(self, g, skip, moments=None):
+        out = np.empty_like(g.f)
+        r, u, a2 = (None, None, None) if moments is None else moments
+        lib().ora_step_ex(C.byref(g.g), g._mask_ptr, _u8p(skip), _dp(g.f), _dp(out), g.t + 1,
+                          _dp(r), _dp(u), _dp(a2))
+        g.f = out
+        g.t += 1
+
+    def step(self, n=1):
+        for _ in range(n):
+            self._sweep(self.coarse, self.cskip, self.M_next)
+            self._sweep(self.fine, self.fring)
+            self._fill_ring(self.M_prev, 0.5, self.M_next, 0.5)
+            self._sweep(self.fine, self.fring, self.mf)
+            self._fill_ring(self.M_next, 1.0, self.M_next, 0.0)
+            lib().ora_ref_import(C.byref(self.R), _u8p(self.crole), _dp(self.mf[0]),
+                                 _dp(self.mf[1]), _dp(self.mf[2]), _dp(self.coarse.f))
+            self.M_prev = [a.copy() for a in self.M_next]
+            self.t += 1
+        return self

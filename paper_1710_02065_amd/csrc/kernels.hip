@@ -36,6 +36,58 @@ __device__ __forceinline__ int dir_rt(int x, int y, int z) {
 }
 
 // ------------------------------------------------------------------------
+// Pull of all populations of cell (x, y, z) under the face rules and the
+// mask (left side of eq. optimizedLB read backwards): the source of
+// population i is x - xi_i, mapped axis by axis (periodic wrap, free-slip
+// reflection with the population mirrored, zero-gradient clamp); a link
+// whose source is SOLID is bounced back halfway from this cell.
+// ------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
+                                             uint32_t y, uint32_t z, uint32_t c,
+                                             typename S::R h[L::Q]) {
+  using R = typename S::R;
+  const uint64_t P = a.pstride;
+  const uint32_t dims[3] = {a.nx, a.ny, a.nz};
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr Dir v = L::dir(i);
+    constexpr int vv[3] = {v.x, v.y, v.z};
+    int32_t s[3] = {(int32_t)x - v.x, (int32_t)y - v.y, (int32_t)z - v.z};
+    bool flip[3] = {false, false, false};
+#pragma unroll
+    for (int ax = 0; ax < L::D; ++ax) {
+      if (vv[ax] == 0) continue;
+      const int32_t n = (int32_t)dims[ax];
+      const bool lo = s[ax] < 0, hi = s[ax] >= n;
+      if (lo || hi) {
+        const int32_t bc = a.face[2 * ax + (hi ? 1 : 0)];
+        if (bc == kPeriodic) {
+          s[ax] = lo ? s[ax] + n : s[ax] - n;
+        } else {
+          s[ax] = lo ? 0 : n - 1;
+          flip[ax] = (bc == kFreeSlip);
+        }
+      }
+    }
+    const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
+    const R wr = (R)L::w(i) * a.rho0;
+    if (a.mask && a.mask[src] == kSolid) {
+      // halfway bounce-back: the population that left this cell towards
+      // the wall comes back reversed
+      constexpr int o = opposite<L>(i);
+      h[i] = decode<S>(a.src[(uint64_t)o * P + c], wr);
+    } else {
+      int pop = i;
+      if (flip[0] || flip[1] || flip[2])
+        pop = dir_rt<L>(flip[0] ? -v.x : v.x, flip[1] ? -v.y : v.y,
+                        flip[2] ? -v.z : v.z);
+      h[i] = decode<S>(a.src[(uint64_t)pop * P + src], wr);
+    }
+  });
+}
+
+// ------------------------------------------------------------------------
 // The sweep: pull-stream + (sponge) + regularized collision + store.
 // kGeneral = false: every face periodic, no mask, no sponge.
 // ------------------------------------------------------------------------
@@ -86,7 +138,7 @@ __global__ void __launch_bounds__(1024)
   } else {
     uint8_t m = kFluid;
     if (a.mask) m = a.mask[c];
-    if (m == kSolid) return;
+    if (m == kSolid || m >= kCovered) return;
     if (m == kInlet) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
@@ -107,47 +159,24 @@ __global__ void __launch_bounds__(1024)
       });
       return;
     }
-    const uint32_t dims[3] = {a.nx, a.ny, a.nz};
-    static_for<0, Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      constexpr Dir v = L::dir(i);
-      constexpr int vv[3] = {v.x, v.y, v.z};
-      int32_t s[3] = {(int32_t)x - v.x, (int32_t)y - v.y, (int32_t)z - v.z};
-      bool flip[3] = {false, false, false};
-#pragma unroll
-      for (int ax = 0; ax < L::D; ++ax) {
-        if (vv[ax] == 0) continue;
-        const int32_t n = (int32_t)dims[ax];
-        const bool lo = s[ax] < 0, hi = s[ax] >= n;
-        if (lo || hi) {
-          const int32_t bc = a.face[2 * ax + (hi ? 1 : 0)];
-          if (bc == kPeriodic) {
-            s[ax] = lo ? s[ax] + n : s[ax] - n;
-          } else {
-            s[ax] = lo ? 0 : n - 1;
-            flip[ax] = (bc == kFreeSlip);
-          }
-        }
-      }
-      const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
-      const R wr = (R)L::w(i) * a.rho0;
-      if (a.mask && a.mask[src] == kSolid) {
-        // halfway bounce-back: the population that left this cell towards
-        // the wall comes back reversed
-        constexpr int o = opposite<L>(i);
-        h[i] = decode<S>(a.src[(uint64_t)o * P + c], wr);
-      } else {
-        int pop = i;
-        if (flip[0] || flip[1] || flip[2])
-          pop = dir_rt<L>(flip[0] ? -v.x : v.x, flip[1] ? -v.y : v.y,
-                          flip[2] ? -v.z : v.z);
-        h[i] = decode<S>(a.src[(uint64_t)pop * P + src], wr);
-      }
-    });
+    pull_general<L, S>(a, x, y, z, c, h);
     R chi = (R)0;
     if (a.chi_max != (R)0)
       chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
-    rho = collide<L, R, true>(h, a.omega1, a.rho0, chi, a.rho_ref, a.uref, post);
+    if (a.rec) {
+      CellMoments<R> mo;
+      rho = collide<L, R, true>(h, a.omega1, a.rho0, chi, a.rho_ref, a.uref, post, &mo);
+      const int64_t r = record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z);
+      if (r >= 0) {
+        a.rec[r] = mo.drho;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
+      }
+    } else {
+      rho = collide<L, R, true>(h, a.omega1, a.rho0, chi, a.rho_ref, a.uref, post);
+    }
   }
   // stability watchdog: a rare, benign racy store of 1
   if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
@@ -203,7 +232,7 @@ __global__ void k_moments(MomentArgs a) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.ncell) return;
   const T* src = (const T*)a.src;
-  if (a.mask && a.mask[c] == kSolid) {
+  if (a.mask && (a.mask[c] == kSolid || a.mask[c] == kCovered)) {
     if (a.rho_out) a.rho_out[c] = 0.0;
     if (a.u_out)
       for (int k = 0; k < 3; ++k) a.u_out[(uint64_t)k * a.ncell + c] = 0.0;
@@ -236,7 +265,7 @@ __global__ void k_probe(ProbeArgs a) {
     a.rho_out[n] = 0.0;
     return;
   }
-  if (a.mask && a.mask[c] == kSolid) {
+  if (a.mask && (a.mask[c] == kSolid || a.mask[c] == kCovered)) {
     a.rho_out[n] = 0.0;
     return;
   }
@@ -280,10 +309,192 @@ __global__ void k_set_pop(PopArgs a) {
 }
 
 // ------------------------------------------------------------------------
+// Two-level refinement kernels (Sec. II.B)
+// ------------------------------------------------------------------------
+__global__ void k_roles(RolesArgs a) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = a.nx * a.ny * a.nz;
+  if (c >= n) return;
+  const uint32_t p[3] = {c % a.nx, (c / a.nx) % a.ny, c / (a.nx * a.ny)};
+  const uint32_t dims[3] = {a.nx, a.ny, a.nz};
+  if (a.level == 0) {
+    bool inside = true, deep = true;
+    for (int ax = 0; ax < a.dim; ++ax) {
+      const int32_t v = (int32_t)p[ax];
+      if (v < a.lo[ax] + 1 || v > a.hi[ax] - 1) inside = false;
+      if (v < a.lo[ax] + 2 || v > a.hi[ax] - 2) deep = false;
+    }
+    if (inside) a.mask[c] = deep ? kCovered : kImport;
+  } else {
+    bool ring = false;
+    for (int ax = 0; ax < a.dim; ++ax)
+      if (p[ax] == 0 || p[ax] == dims[ax] - 1) ring = true;
+    if (ring) a.mask[c] = kRing;
+  }
+}
+
+// coarse moments at t = 0 taken from the initial fields (NULL fields mean
+// rho0, the inlet velocity and zero, as in the initialisation)
+template <class L, class S>
+__global__ void k_record_fields(RecordFieldsArgs a) {
+  using R = typename S::R;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = a.nx * a.ny * a.nz;
+  if (c >= n) return;
+  const int64_t r = record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, c % a.nx,
+                                       (c / a.nx) % a.ny, c / (a.nx * a.ny));
+  if (r < 0) return;
+  R v[10];
+  v[0] = (R)((a.rho ? a.rho[c] : a.rho0) - a.rho0);
+  for (int k = 0; k < 3; ++k) v[1 + k] = (R)(a.u ? a.u[(uint64_t)k * n + c] : a.uin[k]);
+  for (int k = 0; k < 6; ++k) v[4 + k] = (R)(a.pineq ? a.pineq[(uint64_t)k * n + c] : 0.0);
+  if (L::D == 2) v[3] = v[6] = v[8] = v[9] = (R)0;
+  R* ra = (R*)a.rec_a;
+  R* rb = (R*)a.rec_b;
+  for (int k = 0; k < 10; ++k) {
+    ra[(uint64_t)k * a.rec_n + r] = v[k];
+    rb[(uint64_t)k * a.rec_n + r] = v[k];
+  }
+}
+
+// Interpolation points along one axis for fine index k (eq. couplingFC):
+// the coincident coarse node, or for a midpoint the local cubic
+// (-1, 9, 9, -1)/16 over the four nearest coarse nodes.
+__device__ __forceinline__ int axis_points(int32_t lo, uint32_t k, int32_t pts[4],
+                                           float wts[4]) {
+  if ((k & 1u) == 0) {
+    pts[0] = lo + (int32_t)(k >> 1);
+    wts[0] = 1.0f;
+    return 1;
+  }
+  const int32_t j = lo + (int32_t)(k >> 1);
+  pts[0] = j - 1;
+  pts[1] = j;
+  pts[2] = j + 1;
+  pts[3] = j + 2;
+  wts[0] = -1.0f / 16.0f;
+  wts[1] = 9.0f / 16.0f;
+  wts[2] = 9.0f / 16.0f;
+  wts[3] = -1.0f / 16.0f;
+  return 4;
+}
+
+// RING node state: interpolated rho~, u~, Pi~_neq (cubic in space, linear
+// in time), Pi_neq rescaled by alpha_cf = tau_f / (2 tau_c), then
+// f = f^{eqH}(rho~, u~) + (1 - 1/tau_f) f^{neqH}(alpha_cf Pi~_neq, u~).
+template <class L, class S>
+__global__ void k_ring(RingArgs a) {
+  using R = typename S::R;
+  using T = typename S::T;
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.n) return;
+  const uint32_t cf = a.list[n];
+  const uint32_t k[3] = {cf % a.fnx, (cf / a.fnx) % a.fny, cf / (a.fnx * a.fny)};
+  int32_t pts[3][4];
+  float wts[3][4];
+  int np[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax < L::D) {
+      np[ax] = axis_points(a.lo[ax], k[ax], pts[ax], wts[ax]);
+    } else {
+      np[ax] = 1;
+      pts[ax][0] = a.rec_off[ax];
+      wts[ax][0] = 1.0f;
+    }
+  }
+  const R* Ma = (const R*)a.Ma;
+  const R* Mb = (const R*)a.Mb;
+  const R wa = (R)a.wa, wb = (R)a.wb;
+  R m[10];
+  for (int q = 0; q < 10; ++q) m[q] = (R)0;
+  for (int i2 = 0; i2 < np[2]; ++i2)
+    for (int i1 = 0; i1 < np[1]; ++i1)
+      for (int i0 = 0; i0 < np[0]; ++i0) {
+        const uint64_t r =
+            ((uint64_t)(pts[2][i2] - a.rec_off[2]) * a.rec_dim[1] +
+             (uint64_t)(pts[1][i1] - a.rec_off[1])) * a.rec_dim[0] +
+            (uint64_t)(pts[0][i0] - a.rec_off[0]);
+        const R w = (R)wts[0][i0] * (R)wts[1][i1] * (R)wts[2][i2];
+        for (int q = 0; q < 10; ++q) {
+          const uint64_t o = (uint64_t)q * a.rec_n + r;
+          m[q] += w * (wa * Ma[o] + wb * Mb[o]);
+        }
+      }
+  R u[3] = {m[1], m[2], L::D == 3 ? m[3] : (R)0};
+  R a2[6];
+  for (int q = 0; q < 6; ++q) a2[q] = (R)a.alpha * m[4 + q];
+  if (L::D == 2) a2[2] = a2[4] = a2[5] = (R)0;
+  R out[L::Q];
+  rebuild_state<L, R>(m[0], (R)a.rho0, u, a2, (R)a.omega1, out);
+  T* dst = (T*)a.dst;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    dst[(uint64_t)i * a.pstride + cf] = encode<S>(out[i], (R)L::w(i) * (R)a.rho0);
+}
+
+// IMPORT node state (eq. couplingCF): rho, u of the coincident fine node and
+// the (1/4, 1/2, 1/4)-filtered Pi_neq of its 3^D fine neighbours, all
+// pre-collision moments of the fine level at the common time, pulled from
+// the fine state one fine step earlier; Pi_neq rescaled by
+// alpha_fc = 2 tau_c / tau_f; f = f^{eqH}(rho, u) + (1 - 1/tau_c) f^{neqH}.
+template <class L, class S>
+__global__ void k_import(ImportArgs ia) {
+  using R = typename S::R;
+  using T = typename S::T;
+  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ia.n) return;
+  const SweepArgs<S> a = to_args_dev<S>(ia.fine);
+  const uint32_t cc = ia.list[n];
+  const int32_t p[3] = {(int32_t)(cc % ia.cnx), (int32_t)((cc / ia.cnx) % ia.cny),
+                        (int32_t)(cc / (ia.cnx * ia.cny))};
+  int32_t kc[3];
+  for (int ax = 0; ax < 3; ++ax) kc[ax] = ax < L::D ? 2 * (p[ax] - ia.lo[ax]) : 0;
+  const R w1[3] = {(R)0.25, (R)0.5, (R)0.25};
+  const int oz = L::D == 3 ? 1 : 0;
+  R acc[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+  R drho_c = (R)0, u_c[3] = {(R)0, (R)0, (R)0};
+  for (int o2 = -oz; o2 <= oz; ++o2)
+    for (int o1 = -1; o1 <= 1; ++o1)
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        const uint32_t x = (uint32_t)(kc[0] + o0), y = (uint32_t)(kc[1] + o1),
+                       z = (uint32_t)(kc[2] + o2);
+        const uint32_t c = (z * a.ny + y) * a.nx + x;
+        R h[L::Q];
+        pull_general<L, S>(a, x, y, z, c, h);
+        R drho, j[3], P[6], a2[6];
+        raw_moments<L, R>(h, drho, j, P);
+        const R irho = (R)1 / (a.rho0 + drho);
+        const R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
+        noneq_stress<L, R>(drho, j, u, P, a2);
+        const R w = w1[o0 + 1] * w1[o1 + 1] * (oz ? w1[o2 + 1] : (R)1);
+        for (int q = 0; q < 6; ++q) acc[q] += w * a2[q];
+        if (o0 == 0 && o1 == 0 && o2 == 0) {
+          drho_c = drho;
+          for (int q = 0; q < 3; ++q) u_c[q] = u[q];
+        }
+      }
+  for (int q = 0; q < 6; ++q) acc[q] *= (R)ia.alpha;
+  R out[L::Q];
+  rebuild_state<L, R>(drho_c, (R)ia.rho0, u_c, acc, (R)ia.omega1, out);
+  T* dst = (T*)ia.dst;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    dst[(uint64_t)i * ia.pstride + cc] = encode<S>(out[i], (R)L::w(i) * (R)ia.rho0);
+}
+
+// ------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------
 template <class S>
+__host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h);
+
+template <class S>
 static SweepArgs<S> to_args(const SweepHost& h) {
+  return to_args_dev<S>(h);
+}
+
+template <class S>
+__host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
   using T = typename S::T;
   using R = typename S::R;
   SweepArgs<S> a;
@@ -296,8 +507,10 @@ static SweepArgs<S> to_args(const SweepHost& h) {
   a.nz = h.nz;
   a.ncell = h.nx * h.ny * h.nz;
   a.pstride = h.pstride;
+#if !defined(__HIP_DEVICE_COMPILE__)
   a.div_nx = make_fastdiv(h.nx);
   a.div_ny = make_fastdiv(h.ny);
+#endif
   a.omega1 = (R)(1.0 - 1.0 / h.tau);
   a.rho0 = (R)h.rho0;
   a.chi_max = (R)h.chi_max;
@@ -314,6 +527,15 @@ static SweepArgs<S> to_args(const SweepHost& h) {
   a.seed = h.seed;
   a.t_new = h.t_new;
   a.level = h.level;
+  a.ntiles = 0;
+  a.rec = (R*)h.rec;
+  for (int k = 0; k < 3; ++k) {
+    a.rec_off[k] = h.rec_off[k];
+    a.rec_dim[k] = h.rec_dim[k];
+    a.box_lo[k] = h.box_lo[k];
+    a.box_hi[k] = h.box_hi[k];
+  }
+  a.rec_n = h.rec_n;
   return a;
 }
 
@@ -383,5 +605,14 @@ HRLBM_DISPATCH(moments, MomentArgs)
 HRLBM_DISPATCH(probe, ProbeArgs)
 HRLBM_DISPATCH(get_pop, PopArgs)
 HRLBM_DISPATCH(set_pop, PopArgs)
+HRLBM_DISPATCH(record_fields, RecordFieldsArgs)
+HRLBM_DISPATCH(ring, RingArgs)
+HRLBM_DISPATCH(import, ImportArgs)
+
+hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st) {
+  const uint32_t blocks = (n + 255) / 256;
+  if (blocks) hipLaunchKernelGGL(k_roles, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
 
 }  // namespace hrlbm

@@ -23,7 +23,11 @@
 namespace hrlbm {
 
 enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
-enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2 };
+// cell kinds: the public FLUID/SOLID/INLET, and the refinement roles
+// COVERED (coarse node under the fine patch), IMPORT (coarse node rebuilt
+// from fine data), RING (fine node rebuilt from coarse data); cells of the
+// three internal kinds are not swept.
+enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2, kCovered = 3, kImport = 4, kRing = 5 };
 
 // ------------------------------------------------------------------------
 // Division of 32-bit unsigned numbers below 2^31 by a run-time invariant
@@ -119,7 +123,37 @@ struct SweepArgs {
   uint64_t t_new;        // time index of the state being produced
   int32_t level;
   uint32_t ntiles;
+  // refinement: pre-collision moments of the coarse nodes on the patch
+  // boundary planes are recorded into rec (10 components, SoA over the
+  // record box [rec_off, rec_off + rec_dim)); rec == nullptr disables it
+  R* rec;
+  int32_t rec_off[3];
+  uint32_t rec_dim[3];
+  uint32_t rec_n;
+  int32_t box_lo[3], box_hi[3];
 };
+
+// Index into the record box of a coarse node on a patch boundary plane, or
+// -1 if the node is not recorded.  The record box spans [lo - 1, hi + 1] on
+// the active axes; recorded nodes lie on a plane x_a = lo_a or x_a = hi_a.
+template <int D>
+__host__ __device__ inline int64_t record_index(const int32_t off[3],
+                                                const uint32_t dim[3],
+                                                const int32_t lo[3],
+                                                const int32_t hi[3], uint32_t x,
+                                                uint32_t y, uint32_t z) {
+  const int32_t p[3] = {(int32_t)x, (int32_t)y, (int32_t)z};
+  bool on_plane = false;
+  int64_t idx = 0, stride = 1;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int32_t r = p[ax] - off[ax];
+    if (r < 0 || r >= (int32_t)dim[ax]) return -1;
+    idx += (int64_t)r * stride;
+    stride *= dim[ax];
+    if (ax < D && (p[ax] == lo[ax] || p[ax] == hi[ax])) on_plane = true;
+  }
+  return on_plane ? idx : -1;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Re-map the hardware workgroup id so that each XCD walks one
@@ -189,12 +223,11 @@ __device__ __forceinline__ void basis_coeffs(const R m3[7], R bk[L::K]) {
   }
 }
 
-// third-order tensor components of the product v_a w_b w_c symmetrised as
-// in the recursion: returns t_abc = u_a A_bc + u_b A_ac + u_c A_ab for the
-// seven packed components.  A in (xx, yy, zz, xy, xz, yz).
+// Third-order non-equilibrium coefficients from the recursion eq.
+// (recursive2) at n = 3: t_abc = u_a A_bc + u_b A_ac + u_c A_ab for the seven
+// packed components.  A in (xx, yy, zz, xy, xz, yz).
 template <class R>
 __device__ __forceinline__ void recursion3(const R u[3], const R A[6], R t[7]) {
-  // A_ab accessor
   const R xx = A[0], yy = A[1], zz = A[2], xy = A[3], xz = A[4], yz = A[5];
   t[kXXY] = (R)2 * u[0] * xy + u[1] * xx;
   t[kXYY] = (R)2 * u[1] * xy + u[0] * yy;
@@ -218,19 +251,18 @@ __device__ __forceinline__ void cube3(R rho, const R u[3], R t[7]) {
   t[kXYZ] = ruu_x * u[1] * u[2];
 }
 
-// Collision of one cell (eq. optimizedLB, with eqs. spongeLB/dampingLBM and
-// the modified moments at n = m = 1/2 where chi > 0).  h: pre-collision
-// deviations; out: post-collision deviations.  Returns rho* for the
-// stability watchdog.
-template <class L, class R, bool kSponge>
-__device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
-                                     R rho_ref, const R uref[3],
-                                     R out[L::Q]) {
-  constexpr int Q = L::Q;
-  R drho = (R)0, j[3] = {(R)0, (R)0, (R)0};
-  R P[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+// Pre-collision moments of one cell from its deviations h_i = f_i - w_i rho0:
+// drho = sum h, j = sum h xi, P = sum h xi xi (= Pi - rho0 cs^2 I).
+template <class L, class R>
+__device__ __forceinline__ void raw_moments(const R h[L::Q], R& drho, R j[3],
+                                            R P[6]) {
+  drho = (R)0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int a = 0; a < 3; ++a) j[a] = (R)0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) P[a] = (R)0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
     const Dir v = L::dir(i);
     drho += h[i];
     if (v.x) j[0] += (R)v.x * h[i];
@@ -243,6 +275,37 @@ __device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
     if (L::D == 3 && v.x * v.z) P[4] += (R)(v.x * v.z) * h[i];
     if (L::D == 3 && v.y * v.z) P[5] += (R)(v.y * v.z) * h[i];
   }
+}
+
+// a2_neq = Pi - rho cs^2 I - rho u u from the deviation moments
+template <class L, class R>
+__device__ __forceinline__ void noneq_stress(R drho, const R j[3], const R u[3],
+                                             const R P[6], R a2[6]) {
+  a2[0] = P[0] - (R)kCs2 * drho - j[0] * u[0];
+  a2[1] = P[1] - (R)kCs2 * drho - j[1] * u[1];
+  a2[2] = L::D == 3 ? P[2] - (R)kCs2 * drho - j[2] * u[2] : (R)0;
+  a2[3] = P[3] - j[0] * u[1];
+  a2[4] = L::D == 3 ? P[4] - j[0] * u[2] : (R)0;
+  a2[5] = L::D == 3 ? P[5] - j[1] * u[2] : (R)0;
+}
+
+// Moments a collision used: rho* - rho0, u, a2_neq (all pre-collision).
+template <class R>
+struct CellMoments {
+  R drho, u[3], a2[6];
+};
+
+// Collision of one cell (eq. optimizedLB, with eqs. spongeLB/dampingLBM and
+// the modified moments at n = m = 1/2 where chi > 0).  h: pre-collision
+// deviations; out: post-collision deviations.  Returns rho* for the
+// stability watchdog; fills *mo when given.
+template <class L, class R, bool kSponge>
+__device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
+                                     R rho_ref, const R uref[3], R out[L::Q],
+                                     CellMoments<R>* mo = nullptr) {
+  constexpr int Q = L::Q;
+  R drho, j[3], P[6];
+  raw_moments<L, R>(h, drho, j, P);
   if constexpr (kSponge) {
     if (chi != (R)0) {
       const R k = (R)1 / ((R)1 + (R)0.5 * chi);
@@ -256,12 +319,14 @@ __device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
   R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
   // a2_neq = Pi - rho cs^2 I - rho u u  (Pi - rho0 cs^2 I = P)
   R a2[6];
-  a2[0] = P[0] - (R)kCs2 * drho - j[0] * u[0];
-  a2[1] = P[1] - (R)kCs2 * drho - j[1] * u[1];
-  a2[2] = L::D == 3 ? P[2] - (R)kCs2 * drho - j[2] * u[2] : (R)0;
-  a2[3] = P[3] - j[0] * u[1];
-  a2[4] = L::D == 3 ? P[4] - j[0] * u[2] : (R)0;
-  a2[5] = L::D == 3 ? P[5] - j[1] * u[2] : (R)0;
+  noneq_stress<L, R>(drho, j, u, P, a2);
+  if (mo) {
+    mo->drho = drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mo->u[a] = u[a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) mo->a2[a] = a2[a];
+  }
 
   Coeffs<L, R> c;
   R a3n[7], a3e[7];

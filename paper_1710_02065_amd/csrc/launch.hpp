@@ -22,6 +22,67 @@ struct SweepHost {
   uint64_t seed, t_new;
   int32_t level;
   bool general;  // false: all periodic, no mask, no sponge
+  // refinement record of coarse pre-collision moments (nullptr: off)
+  void* rec;
+  int32_t rec_off[3];
+  uint32_t rec_dim[3];
+  uint32_t rec_n;
+  int32_t box_lo[3], box_hi[3];
+};
+
+// Mark the refinement roles in a level's mask: on the coarse level, IMPORT
+// on the shell of [lo+1, hi-1] and COVERED inside it; on the fine level,
+// RING on the outer shell.
+struct RolesArgs {
+  uint8_t* mask;
+  uint32_t nx, ny, nz;
+  int32_t level, dim;
+  int32_t lo[3], hi[3];
+};
+
+// Record box of the coarse moments filled from the initial fields.
+struct RecordFieldsArgs {
+  const double* rho;
+  const double* u;
+  const double* pineq;
+  void* rec_a;
+  void* rec_b;
+  uint32_t nx, ny, nz;
+  int32_t rec_off[3];
+  uint32_t rec_dim[3];
+  uint32_t rec_n;
+  int32_t box_lo[3], box_hi[3];
+  double rho0, uin[3];
+};
+
+// RING nodes of the fine level rebuilt from the recorded coarse moments
+// blended in time (wa * Ma + wb * Mb).
+struct RingArgs {
+  const uint32_t* list;
+  uint32_t n;
+  uint32_t fnx, fny;
+  int32_t lo[3];
+  const void* Ma;
+  const void* Mb;
+  double wa, wb;
+  int32_t rec_off[3];
+  uint32_t rec_dim[3];
+  uint32_t rec_n;
+  double alpha, omega1, rho0;
+  void* dst;
+  uint64_t pstride;
+};
+
+// IMPORT nodes of the coarse level rebuilt from the fine state.
+struct ImportArgs {
+  const uint32_t* list;
+  uint32_t n;
+  uint32_t cnx, cny;
+  int32_t lo[3];
+  SweepHost fine;  // src: fine post-collision state one fine step earlier
+  double alpha, omega1, rho0;
+  void* dst;
+  uint64_t pstride;
 };
 
 struct InitArgs {
@@ -79,5 +140,12 @@ hipError_t launch_get_pop(int lattice, int storage, const PopArgs& a,
                           uint32_t n, hipStream_t st);
 hipError_t launch_set_pop(int lattice, int storage, const PopArgs& a,
                           uint32_t n, hipStream_t st);
+hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st);
+hipError_t launch_record_fields(int lattice, int storage, const RecordFieldsArgs& a,
+                                uint32_t n, hipStream_t st);
+hipError_t launch_ring(int lattice, int storage, const RingArgs& a, uint32_t n,
+                       hipStream_t st);
+hipError_t launch_import(int lattice, int storage, const ImportArgs& a, uint32_t n,
+                         hipStream_t st);
 
 }  // namespace hrlbm

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -49,12 +50,17 @@ size_t storage_bytes(int storage) {
   return 0;
 }
 
-// Population stride: a multiple of 128 elements, plus 128 so that large
-// power-of-two grids do not put every population at the same offset
-// modulo the HBM channel interleave.
+// Population stride: a multiple of 128 elements, plus a pad (128 elements
+// unless HRLBM_POP_PAD says otherwise) on large grids so that power-of-two
+// grids do not put every population at the same offset modulo the HBM
+// channel interleave.
 uint64_t pop_stride(uint64_t n) {
+  static const long pad = [] {
+    const char* s = std::getenv("HRLBM_POP_PAD");
+    return s ? std::atol(s) : 128L;
+  }();
   uint64_t p = align_up(n, 128);
-  if (n >= (1u << 20)) p += 128;
+  if (n >= (1u << 20)) p += (uint64_t)(pad < 0 ? 0 : pad);
   return p;
 }
 
@@ -458,6 +464,10 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   e = launch_init(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "init launch");
   L.has_mask = mask != nullptr;
+  if (ctx->nlevels > 1) {
+    rc = refined_init_level(ctx, level, rho, u, pi_neq);
+    if (rc != LBM_OK) return rc;
+  }
   if (mask) {
     // inlet cells draw noise: note whether any exist (host scan of a copy)
     std::vector<uint8_t> hm((size_t)L.N);
@@ -510,6 +520,11 @@ int lbm_sync(lbm_ctx* ctx) {
 }
 
 int64_t lbm_time(const lbm_ctx* ctx) { return ctx ? ctx->t : -1; }
+
+int64_t lbm_updates_per_step(const lbm_ctx* ctx) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  return ctx->nlevels > 1 ? refined_updates_per_step(ctx) : ctx->lv[0].N;
+}
 
 int lbm_level_shape(const lbm_ctx* ctx, int level, int64_t* nx, int64_t* ny,
                     int64_t* nz) {
@@ -592,6 +607,10 @@ int lbm_get_populations(lbm_ctx* ctx, int level, double* out) {
 int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
   int rc = check_ready(ctx);
   if (rc != LBM_OK) return rc;
+  if (ctx->nlevels > 1)
+    return set_error(LBM_EUNSUPPORTED,
+                     "set_populations on a refined context: the interface moments of the "
+                     "previous coarse step cannot be rebuilt from populations");
   if (level < 0 || level >= ctx->nlevels || !in)
     return set_error(LBM_EINVAL, "level %d / input", level);
   rc = ensure_device(ctx);

@@ -85,7 +85,10 @@ int validate_refinement(const lbm_config& c);
 int make_fine_level(lbm_ctx* ctx);
 size_t plan_interface_layout(lbm_ctx* ctx, size_t off);
 void assign_interface_pointers(lbm_ctx* ctx);
+int refined_init_level(lbm_ctx* ctx, int level, const double* rho, const double* u,
+                       const double* pineq);
 int refined_after_init(lbm_ctx* ctx);
+int64_t refined_updates_per_step(const lbm_ctx* ctx);
 int refined_after_set(lbm_ctx* ctx, int level);
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st);
 void free_refinement(lbm_ctx* ctx);

@@ -28,7 +28,8 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
 
 # every symbol the header declares
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",
-           "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_level_shape",
+           "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
+           "lbm_level_shape",
            "lbm_moments", "lbm_probe", "lbm_get_populations", "lbm_set_populations",
            "lbm_step_batch", "lbm_autotune", "lbm_destroy", "lbm_lattice_table",
            "lbm_last_error"]
@@ -78,6 +79,8 @@ def lib():
         L.lbm_sync.argtypes = [vp]
         L.lbm_time.argtypes = [vp]
         L.lbm_time.restype = i64
+        L.lbm_updates_per_step.argtypes = [vp]
+        L.lbm_updates_per_step.restype = i64
         L.lbm_level_shape.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.lbm_moments.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_probe.argtypes = [vp, C.c_int, vp, C.c_int, dp]
@@ -140,6 +143,10 @@ def lbm_sync(ctx):
 
 def lbm_time(ctx):
     return int(lib().lbm_time(ctx))
+
+
+def lbm_updates_per_step(ctx):
+    return _check(int(lib().lbm_updates_per_step(ctx)))
 
 
 def lbm_level_shape(ctx, level):
@@ -282,6 +289,10 @@ class Simulation:
     @property
     def time(self):
         return lbm_time(self.ctx)
+
+    @property
+    def updates_per_step(self):
+        return lbm_updates_per_step(self.ctx)
 
     def moments(self, level=0):
         t = self.torch

@@ -72,3 +72,22 @@ def run_both(case, steps, storage="f64", rho=None, u=None, pineq=None, **kw):
     sim.sync()
     g = oracle_grid(case).init(rho, u, pineq).step(steps)
     return gf, g.f, sim, g
+
+
+def refined_pair(case):
+    """Oracle RefinedGrid and GPU Simulation for a refined case (keys as
+    above plus lo, hi, and optional fine_mask)."""
+    nx, ny, nz = case["shape"]
+    og = O.RefinedGrid(case["q"], nx, ny, nz, lo=case["lo"], hi=case["hi"],
+                       tau=case.get("tau", 0.6), rho0=case.get("rho0", 1.0),
+                       u_in=inlet_velocity(case), face_bc=case.get("face_bc", (0,) * 6),
+                       sponge_width=case.get("sponge_width", (0,) * 6),
+                       chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
+                       u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
+                       inlet_noise=case.get("inlet_noise", 0.0), mask=case.get("mask"),
+                       fine_mask=case.get("fine_mask"))
+    return og
+
+
+def refined_sim(case, storage="f64", **kw):
+    return gpu_sim(case, storage, refine_lo=tuple(case["lo"]), refine_hi=tuple(case["hi"]), **kw)

@@ -88,3 +88,26 @@ def test_create_without_device_reports_error():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create(lbm.make_config())
     assert e.value.code in (lbm.LBM_EDEVICE, lbm.LBM_EINVAL)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(refine_lo=(2, 10, 10), refine_hi=(20, 30, 30)), "must lie"),
+    (dict(refine_lo=(10, 10, 10), refine_hi=(12, 30, 30)), "< 4"),
+    (dict(refine_lo=(10, 10, 10), refine_hi=(60, 30, 30)), "must lie"),
+    (dict(refine_lo=(10, 10, 10), refine_hi=(30, 30, 30), sponge_width=(12, 0, 0, 0, 0, 0)),
+     "absorbing"),
+    (dict(lattice=9, shape=(64, 64, 1), refine_lo=(10, 10, 1), refine_hi=(30, 30, 1)), "z range"),
+])
+def test_invalid_refinement_rejected(bad, msg):
+    kw = dict(lattice=19, shape=(64, 64, 64))
+    kw.update(bad)
+    assert required(**kw) == 0
+    assert msg.lower() in lbm.lbm_last_error().lower()
+
+
+def test_refined_required_bytes_counts_fine_level():
+    base = required(lattice=19, shape=(64, 64, 64), storage="f32")
+    ref = required(lattice=19, shape=(64, 64, 64), storage="f32", refine_lo=(10, 10, 10),
+                   refine_hi=(30, 30, 30))
+    fine = 41 ** 3 * 19 * 4 * 2
+    assert ref >= base + fine

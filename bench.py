@@ -115,6 +115,33 @@ def cpu_baseline(n, seconds):
                        "(%.1f s) after initialisation" % (n, steps, dt))
 
 
+def serving_bench(n_jobs, step_scale, load, budget_gib, quantum):
+    """Continuous-batching serving of the D2Q9 job mix: first all jobs at
+    t = 0 (saturated throughput), then a seeded Poisson stream offered at
+    `load` times that throughput; p50/p99 latency from arrival to result."""
+    from paper_1710_02065_amd import serve
+    from paper_1710_02065_amd import workloads as W
+    be = serve.GpuBackend()
+    budget = int(budget_gib * 2 ** 30)
+    warm = W.serving_jobs(4, 99, 1e9, side_range=(128, 256), step_range=(40, 80))
+    serve.Server(be, budget, quantum).run(warm)
+    sat_jobs = W.serving_jobs(n_jobs, 5, 1e9, step_scale=step_scale)
+    sat = serve.Server(be, budget, quantum).run(sat_jobs).summary()
+    work = sum(j["nx"] * j["ny"] * j["steps"] for j in sat_jobs) / len(sat_jobs)
+    rate = load * sat["mlups"] * 1e6 / work
+    jobs = W.serving_jobs(n_jobs, 5, rate, step_scale=step_scale)
+    st = serve.Server(be, budget, quantum).run(jobs).summary()
+    return dict(
+        workload="D2Q9 job mix: half cylinder channels, half acoustic pulses, sides U{256..2048}, "
+                 "Ma U[0.05, 0.3], steps U{2000..20000} x %g, half FP32 / half FP16-shifted "
+                 "storage, Poisson arrivals (seed 5)" % step_scale,
+        jobs=n_jobs, offered_load=load, arrival_rate_per_s=round(rate, 3),
+        p50_latency_s=round(st["p50_latency_s"], 4), p99_latency_s=round(st["p99_latency_s"], 4),
+        p50_queue_s=round(st["p50_queue_s"], 4), mlups=round(st["mlups"], 1),
+        saturated_mlups=round(sat["mlups"], 1), budget_gib=budget_gib, quantum_steps=quantum,
+        peak_resident_gib=round(st["peak_bytes"] / 2 ** 30, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +152,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=48)
+    ap.add_argument("--serve-step-scale", type=float, default=0.1)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-quantum", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +254,11 @@ def main():
         out["precision_vs_f64_build"] = precision
     del sim32
     torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("serving: %d jobs, step scale %g" % (args.serve_jobs, args.serve_step_scale))
+        out["serving"] = serving_bench(args.serve_jobs, args.serve_step_scale, args.serve_load,
+                                       args.serve_budget_gib, args.serve_quantum)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)

@@ -4,6 +4,7 @@ hipcc cross-compiles without a GPU.  All HIP sources are compiled with packed
 FP32 instructions disabled.
 """
 import os
+import shutil
 import subprocess
 import sys
 import tempfile
@@ -27,23 +28,27 @@ def build(jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
+        log = open(obj + ".log", "w")  # a file, not a pipe: no back-pressure
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        procs.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
         objs.append(obj)
-        if len([p for p in procs if p[1].poll() is None]) >= jobs:
-            procs[0][1].wait()
+        while len([p for p in procs if p[1].poll() is None]) >= jobs:
+            next(p for p in procs if p[1].poll() is None)[1].wait()
     failed = []
-    for src, p in procs:
-        out = p.communicate()[0].decode(errors="replace")
-        lines = [l for l in out.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+    for src, p, log in procs:
+        p.wait()
+        log.close()
+        with open(log.name, errors="replace") as f:
+            lines = [l for l in f.read().splitlines() if "packed-fp32-ops" not in l and l.strip()]
         if p.returncode != 0:
             failed.append(src)
-            sys.stderr.write("\n".join(lines) + "\n")
+            sys.stderr.write("\n".join(lines[-200:]) + "\n")
     if failed:
         raise RuntimeError("HIP compilation failed: %s" % ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.run([HIPCC, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
+    shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

@@ -17,6 +17,10 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// sweep arguments of one storage format from the format-neutral host block
+template <class S>
+__host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h);
+
 // direction index for a velocity given at run time (only used after a
 // free-slip reflection)
 template <class L>
@@ -92,14 +96,9 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
 // kGeneral = false: every face periodic, no mask, no sponge.
 // ------------------------------------------------------------------------
 template <class L, class S, bool kGeneral>
-__global__ void __launch_bounds__(1024)
-    k_sweep(const SweepArgs<S> a) {
+__device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   using R = typename S::R;
-  using T = typename S::T;
   constexpr int Q = L::Q;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t c = tile * blockDim.x + threadIdx.x;
-  if (c >= a.ncell) return;
   const uint32_t row = fast_div(c, a.div_nx);
   const uint32_t x = c - row * a.nx;
   const uint32_t z = fast_div(row, a.div_ny);
@@ -185,6 +184,15 @@ __global__ void __launch_bounds__(1024)
     const R wr = (R)L::w(i) * a.rho0;
     __builtin_nontemporal_store(encode<S>(post[i], wr), &a.dst[(uint64_t)i * P + c]);
   });
+}
+
+template <class L, class S, bool kGeneral>
+__global__ void __launch_bounds__(1024)
+    k_sweep(const SweepArgs<S> a) {
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t c = tile * blockDim.x + threadIdx.x;
+  if (c >= a.ncell) return;
+  sweep_cell<L, S, kGeneral>(a, c);
 }
 
 // ------------------------------------------------------------------------
@@ -306,6 +314,59 @@ __global__ void k_set_pop(PopArgs a) {
     dst[(uint64_t)i * a.pstride + c] = v;
     if (dst2) dst2[(uint64_t)i * a.pstride + c] = v;
   }
+}
+
+// ------------------------------------------------------------------------
+// Persistent batched sweep (serving): a fixed grid walks the (job, tile)
+// work list of every resident context; the step index comes from device
+// memory, so a captured sequence of launches replays for any job table.
+// Each cell runs the same sweep_cell instantiation as a solo launch of its
+// context, so results are bitwise those of lbm_step.
+// ------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_t c) {
+  SweepArgs<S> a = to_args_dev<S>(J.h);
+  const int p = (J.cur0 + s) & 1;
+  a.src = (const typename S::T*)J.buf[p];
+  a.dst = (typename S::T*)J.buf[p ^ 1];
+  a.t_new = J.t0 + (uint64_t)s + 1ull;
+  a.ncell = J.h.nx * J.h.ny * J.h.nz;
+  a.div_nx = FastDiv{J.div_nx[0], J.div_nx[1], J.div_nx[2]};
+  a.div_ny = FastDiv{J.div_ny[0], J.div_ny[1], J.div_ny[2]};
+  if (J.h.general)
+    sweep_cell<L, S, true>(a, c);
+  else
+    sweep_cell<L, S, false>(a, c);
+}
+
+template <class L>
+__global__ void __launch_bounds__(1024) k_batch(const BatchJob* __restrict__ jobs,
+                                                const BatchHeader* __restrict__ hdr) {
+  const int32_t s = hdr->step;
+  const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
+  const uint32_t first = xcd_tile(blockIdx.x, gridDim.x);
+  for (uint32_t tile = first; tile < total; tile += gridDim.x) {
+    // last job whose first tile is <= tile
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid;
+    }
+    const BatchJob& J = jobs[lo];
+    if ((int64_t)s >= J.steps) continue;
+    const uint32_t c = (tile - J.tile_begin) * blockDim.x + threadIdx.x;
+    if (c >= J.h.nx * J.h.ny * J.h.nz) continue;
+    switch (J.storage) {
+      case 0: batch_cell<L, StoreF64>(J, s, c); break;
+      case 1: batch_cell<L, StoreF32>(J, s, c); break;
+      case 2: batch_cell<L, StoreF32S>(J, s, c); break;
+      case 3: batch_cell<L, StoreF16S>(J, s, c); break;
+    }
+  }
+}
+
+__global__ void k_batch_bump(BatchHeader* hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->step += 1;
 }
 
 // ------------------------------------------------------------------------
@@ -486,9 +547,6 @@ __global__ void k_import(ImportArgs ia) {
 // Host launchers
 // ------------------------------------------------------------------------
 template <class S>
-__host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h);
-
-template <class S>
 static SweepArgs<S> to_args(const SweepHost& h) {
   return to_args_dev<S>(h);
 }
@@ -608,6 +666,44 @@ HRLBM_DISPATCH(set_pop, PopArgs)
 HRLBM_DISPATCH(record_fields, RecordFieldsArgs)
 HRLBM_DISPATCH(ring, RingArgs)
 HRLBM_DISPATCH(import, ImportArgs)
+
+void fill_fastdiv(uint32_t d, uint32_t out[3]) {
+  const FastDiv f = make_fastdiv(d);
+  out[0] = f.d;
+  out[1] = f.m;
+  out[2] = f.s;
+}
+
+hipError_t launch_batch(int lattice, const BatchJob* jobs, BatchHeader* hdr, int block,
+                        int grid, hipStream_t st) {
+  switch (lattice) {
+    case 9: hipLaunchKernelGGL(k_batch<Lattice<9>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
+    case 19: hipLaunchKernelGGL(k_batch<Lattice<19>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
+    case 27: hipLaunchKernelGGL(k_batch<Lattice<27>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_bump, dim3(1), dim3(64), 0, st, hdr);
+  return hipGetLastError();
+}
+
+int batch_grid(int lattice, int block) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (lattice) {
+    case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<9>>, block, 0); break;
+    case 19: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<19>>, block, 0); break;
+    case 27: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<27>>, block, 0); break;
+  }
+  if (e != hipSuccess || per < 1) per = 1;
+  return cus * per;
+}
 
 hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st) {
   const uint32_t blocks = (n + 255) / 256;

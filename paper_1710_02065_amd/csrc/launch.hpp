@@ -128,8 +128,35 @@ struct PopArgs {
   double rho0;
 };
 
+// One context of a batched (serving) launch.  The job table stays in device
+// memory for the whole batch; the step index s comes from BatchHeader.
+struct BatchJob {
+  SweepHost h;          // parameters; h.src / h.dst unused
+  void* buf[2];         // the context's two population buffers
+  int32_t storage;
+  int32_t cur0;         // buffer holding the state at batch start
+  uint64_t t0;          // time index at batch start
+  int64_t steps;        // steps this job takes in the batch
+  uint32_t tile_begin;  // first tile of this job in the work list
+  uint32_t ntiles;
+  uint32_t div_nx[3], div_ny[3];  // fast-division constants (d, m, s)
+};
+
+struct BatchHeader {
+  uint32_t njobs;
+  uint32_t total_tiles;
+  int32_t step;  // current step index s within the batch
+  int32_t pad;
+};
+
 hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
                         hipStream_t st);
+// persistent batched sweep: grid of `grid` workgroups of `block` threads
+hipError_t launch_batch(int lattice, const BatchJob* jobs, BatchHeader* hdr, int block,
+                        int grid, hipStream_t st);
+hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st);
+int batch_grid(int lattice, int block);  // resident workgroups on the device
+void fill_fastdiv(uint32_t d, uint32_t out[3]);
 hipError_t launch_init(int lattice, int storage, const InitArgs& a, uint32_t n,
                        hipStream_t st);
 hipError_t launch_moments(int lattice, int storage, const MomentArgs& a,

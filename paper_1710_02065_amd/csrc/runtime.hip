@@ -485,6 +485,10 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   L.cur = 0;
   L.t = 0;
   L.initialised = true;
+  if (ctx->cfg.block == 0) {
+    const int tb = tuned_block(ctx);
+    if (tb > 0) ctx->block = tb;
+  }
   ctx->t = 0;
   for (int l = 0; l < ctx->nlevels; ++l) ctx->lv[l].t = 0;
   drop_graphs(ctx);

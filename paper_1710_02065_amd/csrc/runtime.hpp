@@ -80,6 +80,9 @@ SweepHost sweep_args(const lbm_ctx* ctx, int level, int src_buf, uint64_t t_new)
 int sweep_level(lbm_ctx* ctx, int level, hipStream_t st);
 int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st);
 
+// workgroup size from the autotuner cache, 0 if none (serve.hip)
+int tuned_block(const lbm_ctx* ctx);
+
 // two-level refinement (refine.hip)
 int validate_refinement(const lbm_config& c);
 int make_fine_level(lbm_ctx* ctx);

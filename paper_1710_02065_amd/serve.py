@@ -1,0 +1,270 @@
+"""Continuous-batching serving of many small lattices on one GPU.
+
+Jobs (2D D2Q9 cylinder-in-channel or acoustic-pulse lattices of uneven
+sizes) arrive over time.  The server keeps every admitted job's populations
+resident in HBM, admits queued jobs in arrival order whenever their device
+footprint (lbm_required_bytes) fits the remaining budget, and advances all
+resident jobs together: each quantum is one lbm_step_batch call, i.e. one
+persistent batched launch sequence (replayed as hipGraphs) over the (job,
+tile) work list of every resident lattice.  Jobs that arrive while others
+run join at the next quantum; finished jobs release their memory at once.
+
+Backends: `GpuBackend` drives the HIP library; `FakeBackend` is a
+cost-model stand-in with a simulated clock for testing the scheduler on a
+machine without a GPU.
+"""
+import math
+import time
+from dataclasses import dataclass, field
+
+CS = math.sqrt(1.0 / 3.0)
+
+
+@dataclass
+class JobRecord:
+    job: dict
+    need: int = 0
+    admitted: float = -1.0
+    finished: float = -1.0
+    done_steps: int = 0
+    handle: object = None
+    result: object = None
+
+    @property
+    def remaining(self):
+        return self.job["steps"] - self.done_steps
+
+
+@dataclass
+class Stats:
+    latencies: list = field(default_factory=list)
+    queue_delays: list = field(default_factory=list)
+    cell_updates: int = 0
+    makespan: float = 0.0
+    peak_bytes: int = 0
+    quanta: int = 0
+
+    @staticmethod
+    def pct(values, p):
+        if not values:
+            return float("nan")
+        v = sorted(values)
+        k = (len(v) - 1) * p / 100.0
+        f = math.floor(k)
+        c = min(f + 1, len(v) - 1)
+        return v[f] + (v[c] - v[f]) * (k - f)
+
+    def summary(self):
+        return dict(jobs=len(self.latencies),
+                    p50_latency_s=self.pct(self.latencies, 50),
+                    p99_latency_s=self.pct(self.latencies, 99),
+                    p50_queue_s=self.pct(self.queue_delays, 50),
+                    mlups=self.cell_updates / self.makespan / 1e6 if self.makespan > 0 else 0.0,
+                    makespan_s=self.makespan, peak_bytes=self.peak_bytes, quanta=self.quanta)
+
+
+class Server:
+    """Admission + continuous batching loop.
+
+    budget_bytes: HBM budget for resident jobs; quantum: steps per batched
+    call (a job near its end takes only its remaining steps)."""
+
+    def __init__(self, backend, budget_bytes, quantum=256):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.quantum = int(quantum)
+
+    def run(self, jobs):
+        be = self.backend
+        pending = sorted((JobRecord(j) for j in jobs), key=lambda r: r.job["arrival"])
+        for r in pending:
+            r.need = be.required_bytes(r.job)
+            if r.need > self.budget:
+                raise ValueError("job %s needs %d bytes, more than the budget %d"
+                                 % (r.job["id"], r.need, self.budget))
+        queue, active, done = [], [], []
+        used = 0
+        st = Stats()
+        t0 = be.now()
+        while pending or queue or active:
+            now = be.now() - t0
+            while pending and pending[0].job["arrival"] <= now:
+                queue.append(pending.pop(0))
+            # admit in arrival order every queued job that fits
+            for r in list(queue):
+                if used + r.need <= self.budget:
+                    r.handle = be.start(r.job)
+                    r.admitted = be.now() - t0
+                    used += r.need
+                    queue.remove(r)
+                    active.append(r)
+            st.peak_bytes = max(st.peak_bytes, used)
+            if not active:
+                if pending:
+                    be.wait_until(t0 + pending[0].job["arrival"])
+                continue
+            steps = [min(self.quantum, r.remaining) for r in active]
+            be.step([r.handle for r in active], steps)
+            be.sync()
+            st.quanta += 1
+            for r, n in zip(active, steps):
+                r.done_steps += n
+            now = be.now() - t0
+            for r in [r for r in active if r.remaining == 0]:
+                r.result = be.finish(r.handle)
+                r.finished = be.now() - t0
+                used -= r.need
+                active.remove(r)
+                done.append(r)
+                st.latencies.append(r.finished - r.job["arrival"])
+                st.queue_delays.append(r.admitted - r.job["arrival"])
+                st.cell_updates += be.cells(r.job) * r.job["steps"]
+        if done:
+            st.makespan = max(r.finished for r in done) - min(r.job["arrival"] for r in done)
+        self.records = done
+        return st
+
+
+class FakeBackend:
+    """Scheduler test double: fixed throughput, simulated clock, no GPU."""
+
+    def __init__(self, mlups=1000.0, bytes_per_cell=72, launch_overhead=1e-4):
+        self.mlups = mlups
+        self.bpc = bytes_per_cell
+        self.overhead = launch_overhead
+        self.clock = 0.0
+        self.live = {}
+        self.max_live_bytes = 0
+        self.calls = []
+
+    def now(self):
+        return self.clock
+
+    def wait_until(self, t):
+        self.clock = max(self.clock, t)
+
+    def cells(self, job):
+        return job["nx"] * job["ny"]
+
+    def required_bytes(self, job):
+        return self.cells(job) * self.bpc
+
+    def start(self, job):
+        self.live[job["id"]] = self.required_bytes(job)
+        self.max_live_bytes = max(self.max_live_bytes, sum(self.live.values()))
+        return job
+
+    def step(self, handles, steps):
+        work = sum(self.cells(h) * n for h, n in zip(handles, steps))
+        self.clock += self.overhead + work / (self.mlups * 1e6)
+        self.calls.append([(h["id"], n) for h, n in zip(handles, steps)])
+
+    def sync(self):
+        pass
+
+    def finish(self, h):
+        del self.live[h["id"]]
+        return h["id"]
+
+
+class GpuBackend:
+    """Jobs as lbm contexts on one GPU, memory from torch's allocator."""
+
+    def __init__(self, device=0, keep_populations=False):
+        import torch
+
+        from . import lbm
+        self.torch, self.lbm = torch, lbm
+        self.dev = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.dev).cuda_stream
+        self.keep = keep_populations
+
+    def now(self):
+        return time.perf_counter()
+
+    def wait_until(self, t):
+        d = t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+
+    def cells(self, job):
+        return job["nx"] * job["ny"]
+
+    def config(self, job):
+        lbm = self.lbm
+        nx, ny, U = job["nx"], job["ny"], job["ma"] * CS
+        common = dict(lattice=lbm.LBM_D2Q9, shape=(nx, ny, 1), storage=job["storage"],
+                      stream=self.stream, seed=job["seed"])
+        if job["kind"] == "cylinder":
+            D = max(ny // 10, 4)
+            tau = 0.5 + 3.0 * U * D / 150.0
+            W = max(nx // 8, 4)
+            return lbm.make_config(tau=tau, ma=job["ma"], face_bc=(2, 2, 1, 1, 0, 0),
+                                   sponge_width=(0, W, 0, 0, 0, 0), chi_max=0.2, rho_ref=1.0,
+                                   u_ref=(U, 0.0, 0.0), **common)
+        return lbm.make_config(tau=0.55, ma=job["ma"], **common)
+
+    def required_bytes(self, job):
+        return self.lbm.lbm_required_bytes(self.config(job))
+
+    def fields(self, job):
+        """Initial fields on the device: uniform flow U along x with a seeded
+        1e-4 relative perturbation, and for pulse jobs a Gaussian density
+        pulse (1e-3, sigma 8) at the centre; for cylinder jobs the SOLID disc
+        of diameter ny/10 at (nx/5, ny/2) and the INLET column at x = 0."""
+        t = self.torch
+        nx, ny, U = job["nx"], job["ny"], job["ma"] * CS
+        g = t.Generator(device=self.dev)
+        g.manual_seed(job["seed"])
+        y, x = t.meshgrid(t.arange(ny, device=self.dev, dtype=t.float64),
+                          t.arange(nx, device=self.dev, dtype=t.float64), indexing="ij")
+        u = t.zeros(3, ny * nx, dtype=t.float64, device=self.dev)
+        u[0] = U
+        u[:2] += 1e-4 * U * (2 * t.rand(2, ny * nx, generator=g, device=self.dev,
+                                         dtype=t.float64) - 1)
+        rho = t.ones(ny * nx, dtype=t.float64, device=self.dev)
+        mask = None
+        if job["kind"] == "pulse":
+            r2 = (x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2
+            rho += 1e-3 * t.exp(-r2 / (2 * 8.0 ** 2)).reshape(-1)
+        else:
+            D = max(ny // 10, 4)
+            m = ((x - nx / 5.0) ** 2 + (y - ny / 2.0) ** 2 <= (D / 2.0) ** 2).to(t.uint8)
+            m[:, 0] = 2
+            mask = m.reshape(-1).contiguous()
+        return rho, u, mask
+
+    def start(self, job):
+        lbm, t = self.lbm, self.torch
+        cfg = self.config(job)
+        need = lbm.lbm_required_bytes(cfg)
+        mem = t.empty(need, dtype=t.uint8, device=self.dev)
+        ctx = lbm.lbm_create(cfg)
+        lbm.lbm_bind_memory(ctx, mem, need)
+        rho, u, mask = self.fields(job)
+        lbm.lbm_init(ctx, 0, rho, u, None, mask)
+        return dict(ctx=ctx, mem=mem, keep=(rho, u, mask), job=job)
+
+    def step(self, handles, steps):
+        self.lbm.lbm_step_batch([h["ctx"] for h in handles], steps)
+
+    def sync(self):
+        self.torch.cuda.synchronize(self.dev)
+
+    def finish(self, h):
+        lbm, t = self.lbm, self.torch
+        job = h["job"]
+        n = self.cells(job)
+        rho = t.empty(n, dtype=t.float64, device=self.dev)
+        lbm.lbm_moments(h["ctx"], 0, rho, None)
+        out = dict(id=job["id"], rho_mean=None, pops=None)
+        if self.keep:
+            pops = t.empty(9, n, dtype=t.float64, device=self.dev)
+            lbm.lbm_get_populations(h["ctx"], 0, pops)
+            out["pops"] = pops.cpu()
+        out["rho_mean"] = float(rho.mean().item())
+        lbm.lbm_sync(h["ctx"])
+        lbm.lbm_destroy(h["ctx"])
+        h["ctx"] = None
+        del h["mem"], h["keep"]
+        return out

@@ -9,14 +9,6 @@
 
 namespace hrlbm {
 
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
 // sweep arguments of one storage format from the format-neutral host block
 template <class S>
 __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h);
@@ -49,8 +41,7 @@ __device__ __forceinline__ int dir_rt(int x, int y, int z) {
 template <class L, class S>
 __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
                                              uint32_t y, uint32_t z, uint32_t c,
-                                             typename S::R h[L::Q]) {
-  using R = typename S::R;
+                                             typename S::T raw[L::Q]) {
   const uint64_t P = a.pstride;
   const uint32_t dims[3] = {a.nx, a.ny, a.nz};
   static_for<0, L::Q>([&](auto I) {
@@ -75,18 +66,17 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
       }
     }
     const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
-    const R wr = (R)L::w(i) * a.rho0;
     if (a.mask && a.mask[src] == kSolid) {
       // halfway bounce-back: the population that left this cell towards
-      // the wall comes back reversed
+      // the wall comes back reversed (same weight, so the same shift)
       constexpr int o = opposite<L>(i);
-      h[i] = decode<S>(a.src[(uint64_t)o * P + c], wr);
+      raw[i] = load_pop(a.src + (uint64_t)o * P, c);
     } else {
       int pop = i;
       if (flip[0] || flip[1] || flip[2])
         pop = dir_rt<L>(flip[0] ? -v.x : v.x, flip[1] ? -v.y : v.y,
                         flip[2] ? -v.z : v.z);
-      h[i] = decode<S>(a.src[(uint64_t)pop * P + src], wr);
+      raw[i] = load_pop(a.src + (uint64_t)pop * P, src);
     }
   });
 }
@@ -98,16 +88,19 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
 template <class L, class S, bool kGeneral>
 __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   using R = typename S::R;
+  using T = typename S::T;
   constexpr int Q = L::Q;
   const uint32_t row = fast_div(c, a.div_nx);
   const uint32_t x = c - row * a.nx;
   const uint32_t z = fast_div(row, a.div_ny);
   const uint32_t y = row - z * a.ny;
   const uint64_t P = a.pstride;
+  // the rebuilt values are produced directly in the storage domain
+  const R base = S::kShifted ? (R)0 : a.rho0;
 
-  R h[Q];
+  T raw[Q];
   R post[Q];
-  R rho;
+  R rho, drho, j[3], Pm[6];
   if constexpr (!kGeneral) {
     // periodic wrap: offsets to the x-1 / x+1 (etc.) neighbours
     const int32_t nx = (int32_t)a.nx, nxy = (int32_t)(a.nx * a.ny);
@@ -130,10 +123,11 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       if constexpr (v.y < 0) off += oy_p;
       if constexpr (v.z > 0) off += oz_m;
       if constexpr (v.z < 0) off += oz_p;
-      const R wr = (R)L::w(i) * a.rho0;
-      h[i] = decode<S>(a.src[(uint64_t)i * P + (uint32_t)((int32_t)c + off)], wr);
+      raw[i] = load_pop(a.src + (uint64_t)i * P, (uint32_t)((int32_t)c + off));
     });
-    rho = collide<L, R, false>(h, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref, post);
+    stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
+    rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref,
+                                       base, post);
   } else {
     uint8_t m = kFluid;
     if (a.mask) m = a.mask[c];
@@ -141,11 +135,11 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
     if (m == kInlet) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
-      const uint64_t base =
+      const uint64_t bidx =
           ((a.t_new * 2ull + (uint64_t)a.level) * (uint64_t)a.ncell + c) * 3ull;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const R r = (R)splitmix_pm1(a.seed, base + (uint64_t)k);
+        const R r = (R)splitmix_pm1(a.seed, bidx + (uint64_t)k);
         u[k] = a.uin[k] * ((R)1 + a.noise * r);
       }
       if (L::D == 2) u[2] = (R)0;
@@ -158,13 +152,15 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       });
       return;
     }
-    pull_general<L, S>(a, x, y, z, c, h);
+    pull_general<L, S>(a, x, y, z, c, raw);
+    stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
     R chi = (R)0;
     if (a.chi_max != (R)0)
       chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
     if (a.rec) {
       CellMoments<R> mo;
-      rho = collide<L, R, true>(h, a.omega1, a.rho0, chi, a.rho_ref, a.uref, post, &mo);
+      rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
+                                        base, post, &mo);
       const int64_t r = record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z);
       if (r >= 0) {
         a.rec[r] = mo.drho;
@@ -174,23 +170,26 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
         for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
       }
     } else {
-      rho = collide<L, R, true>(h, a.omega1, a.rho0, chi, a.rho_ref, a.uref, post);
+      rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
+                                        base, post);
     }
   }
   // stability watchdog: a rare, benign racy store of 1
   if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    const R wr = (R)L::w(i) * a.rho0;
-    __builtin_nontemporal_store(encode<S>(post[i], wr), &a.dst[(uint64_t)i * P + c]);
+    store_pop_nt(a.dst + (uint64_t)i * P, (uint32_t)(P * sizeof(T)), c, (T)post[i]);
   });
 }
 
 template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
     k_sweep(const SweepArgs<S> a) {
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t c = tile * blockDim.x + threadIdx.x;
+  // Tile b goes to workgroup b: the hardware deals workgroups round-robin
+  // to the eight XCDs, so all XCDs stream through neighbouring tiles at the
+  // same time (measured faster here than giving each XCD a contiguous eighth
+  // of the grid: this sweep shares no data between tiles through L2).
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.ncell) return;
   sweep_cell<L, S, kGeneral>(a, c);
 }
@@ -344,8 +343,7 @@ __global__ void __launch_bounds__(1024) k_batch(const BatchJob* __restrict__ job
                                                 const BatchHeader* __restrict__ hdr) {
   const int32_t s = hdr->step;
   const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
-  const uint32_t first = xcd_tile(blockIdx.x, gridDim.x);
-  for (uint32_t tile = first; tile < total; tile += gridDim.x) {
+  for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
     // last job whose first tile is <= tile
     uint32_t lo = 0, hi = njobs;
     while (hi - lo > 1) {
@@ -520,11 +518,11 @@ __global__ void k_import(ImportArgs ia) {
         const uint32_t x = (uint32_t)(kc[0] + o0), y = (uint32_t)(kc[1] + o1),
                        z = (uint32_t)(kc[2] + o2);
         const uint32_t c = (z * a.ny + y) * a.nx + x;
-        R h[L::Q];
-        pull_general<L, S>(a, x, y, z, c, h);
+        T raw[L::Q];
+        pull_general<L, S>(a, x, y, z, c, raw);
         R drho, j[3], P[6], a2[6];
-        raw_moments<L, R>(h, drho, j, P);
-        const R irho = (R)1 / (a.rho0 + drho);
+        stored_moments<L, S>(raw, a.rho0, drho, j, P);
+        const R irho = recip(a.rho0 + drho);
         const R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
         noneq_stress<L, R>(drho, j, u, P, a2);
         const R w = w1[o0 + 1] * w1[o1 + 1] * (oz ? w1[o2 + 1] : (R)1);

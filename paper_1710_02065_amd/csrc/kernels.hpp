@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lattice.hpp"
 
@@ -99,6 +100,38 @@ __device__ __forceinline__ typename S::T encode(typename S::R h,
     return (T)(h + wrho0);
 }
 
+// Element idx of the population array starting at `base`, addressed as a
+// uniform 64-bit base plus a 32-bit byte offset (every population array is
+// smaller than 4 GiB; checked when a context is created), which maps onto
+// the scalar-base global memory instructions.
+template <class T>
+__device__ __forceinline__ T load_pop(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+// Non-temporal store of element idx of a population array through a raw
+// buffer resource (scalar base, 32-bit offset, stores past `bytes` are
+// dropped by the hardware).  The third resource word 0x00020000 is the
+// gfx9-family untyped 32-bit data format.
+template <class T>
+__device__ __forceinline__ void store_pop_nt(T* base, uint32_t bytes, uint32_t idx, T v) {
+  __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+  constexpr int kNonTemporal = 2;
+  const uint32_t off = idx * (uint32_t)sizeof(T);
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0,
+                                          kNonTemporal);
+  }
+  else if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0,
+                                          kNonTemporal);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, off, 0,
+                                          kNonTemporal);
+}
+
 // ------------------------------------------------------------------------
 // Kernel arguments
 // ------------------------------------------------------------------------
@@ -155,17 +188,6 @@ __host__ __device__ inline int64_t record_index(const int32_t off[3],
   return on_plane ? idx : -1;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Re-map the hardware workgroup id so that each XCD walks one
-// contiguous range of tiles: cache lines shared by neighbouring tiles then
-// stay within one L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
-  constexpr uint32_t kXcd = 8;
-  const uint32_t per = n / kXcd, rem = n % kXcd;
-  const uint32_t x = b % kXcd, k = b / kXcd;
-  return x * per + (x < rem ? x : rem) + k;
-}
-
 // ------------------------------------------------------------------------
 // Regularized rebuild (eqs. eqH, neqH, optimizedLB) from Hermite
 // coefficients.  With the combined coefficients
@@ -182,33 +204,58 @@ struct Coeffs {
   R m3[7];  // xxy, xyy, xxz, xzz, yyz, yzz, xyz
 };
 
-template <class L, class R>
-__device__ __forceinline__ R rebuild_one(const Coeffs<L, R>& c, R bk[L::K],
-                                         int i) {
-  constexpr R inv_cs2 = (R)3.0, half_inv_cs4 = (R)4.5;
-  const Dir v = L::dir(i);
-  R s = c.m0;
-  R lin = (R)0;
-  if (v.x) lin += (R)v.x * c.m1[0];
-  if (v.y) lin += (R)v.y * c.m1[1];
-  if (L::D == 3 && v.z) lin += (R)v.z * c.m1[2];
-  s += inv_cs2 * lin;
-  // H2(xi):m2 = sum_ab xi_a xi_b m2_ab - cs^2 tr(m2)
-  R tr = c.m2[0] + c.m2[1] + (L::D == 3 ? c.m2[2] : (R)0);
-  R q2 = -(R)kCs2 * tr;
-  if (v.x) q2 += c.m2[0];
-  if (v.y) q2 += c.m2[1];
-  if (L::D == 3 && v.z) q2 += c.m2[2];
-  if (v.x * v.y) q2 += (R)(2 * v.x * v.y) * c.m2[3];
-  if (L::D == 3 && v.x * v.z) q2 += (R)(2 * v.x * v.z) * c.m2[4];
-  if (L::D == 3 && v.y * v.z) q2 += (R)(2 * v.y * v.z) * c.m2[5];
-  s += half_inv_cs4 * q2;
-#pragma unroll
-  for (int k = 0; k < L::K; ++k) {
-    const double hk = basis_h<L>(i, k);
-    if (hk != 0.0) s += (R)hk * bk[k];
+// Compile-time loop (the index is a constant in the body).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
   }
-  return (R)L::w(i) * s;
+}
+
+// All q populations from the coefficients.  Directions come in opposite
+// pairs (2k-1, 2k) with xi_{2k} = -xi_{2k-1}: the zeroth- and second-order
+// terms are even in xi, the first- and third-order terms odd, so each pair
+// costs one even and one odd sum.  `base` is added to m0 (rho0 when the
+// stored value is f itself, 0 when it is the deviation from rest).
+template <class L, class R>
+__device__ __forceinline__ void rebuild_all(const Coeffs<L, R>& c, const R bk[L::K], R base,
+                                            R out[L::Q]) {
+  const R tr = c.m2[0] + c.m2[1] + (L::D == 3 ? c.m2[2] : (R)0);
+  // even part at xi = 0: m0 - cs^2 tr / (2 cs^4) = m0 - 1.5 tr
+  const R e0 = base + c.m0 - (R)1.5 * tr;
+  const R m1s[3] = {(R)3 * c.m1[0], (R)3 * c.m1[1], (R)3 * c.m1[2]};
+  const R d2[3] = {(R)4.5 * c.m2[0], (R)4.5 * c.m2[1], (R)4.5 * c.m2[2]};
+  const R o2[3] = {(R)9 * c.m2[3], (R)9 * c.m2[4], (R)9 * c.m2[5]};
+  out[0] = (R)L::w(0) * e0;
+  static_for<0, (L::Q - 1) / 2>([&](auto K) {
+    constexpr int i = 1 + 2 * decltype(K)::value;
+    constexpr Dir v = L::dir(i);
+    R even = e0;
+    if constexpr (v.x != 0) even += d2[0];
+    if constexpr (v.y != 0) even += d2[1];
+    if constexpr (v.z != 0) even += d2[2];
+    if constexpr (v.x * v.y > 0) even += o2[0];
+    if constexpr (v.x * v.y < 0) even -= o2[0];
+    if constexpr (v.x * v.z > 0) even += o2[1];
+    if constexpr (v.x * v.z < 0) even -= o2[1];
+    if constexpr (v.y * v.z > 0) even += o2[2];
+    if constexpr (v.y * v.z < 0) even -= o2[2];
+    R odd = (R)0;
+    if constexpr (v.x > 0) odd += m1s[0];
+    if constexpr (v.x < 0) odd -= m1s[0];
+    if constexpr (v.y > 0) odd += m1s[1];
+    if constexpr (v.y < 0) odd -= m1s[1];
+    if constexpr (v.z > 0) odd += m1s[2];
+    if constexpr (v.z < 0) odd -= m1s[2];
+    static_for<0, L::K>([&](auto KK) {
+      constexpr double hk = basis_h<L>(i, decltype(KK)::value);
+      if constexpr (hk != 0.0) odd += (R)hk * bk[decltype(KK)::value];
+    });
+    constexpr R w = (R)L::w(i);
+    out[i] = w * (even + odd);
+    out[i + 1] = w * (even - odd);
+  });
 }
 
 // third-order set -> basis coefficients c_k / N_k
@@ -251,30 +298,83 @@ __device__ __forceinline__ void cube3(R rho, const R u[3], R t[7]) {
   t[kXYZ] = ruu_x * u[1] * u[2];
 }
 
-// Pre-collision moments of one cell from its deviations h_i = f_i - w_i rho0:
-// drho = sum h, j = sum h xi, P = sum h xi xi (= Pi - rho0 cs^2 I).
+// Pre-collision moments of one cell from the pair sums s = h_i + h_{i+1} and
+// differences d = h_i - h_{i+1} of its deviations h = f - w rho0:
+// drho = sum h, j = sum h xi = sum d xi_i, P = sum h xi xi = sum s xi_i xi_i
+// (P = Pi - rho0 cs^2 I).
 template <class L, class R>
-__device__ __forceinline__ void raw_moments(const R h[L::Q], R& drho, R j[3],
-                                            R P[6]) {
-  drho = (R)0;
+__device__ __forceinline__ void pair_moments(R h0, const R s[(L::Q - 1) / 2],
+                                             const R d[(L::Q - 1) / 2], R& drho, R j[3],
+                                             R P[6]) {
+  drho = h0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) j[a] = (R)0;
 #pragma unroll
   for (int a = 0; a < 6; ++a) P[a] = (R)0;
+  static_for<0, (L::Q - 1) / 2>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr Dir v = L::dir(1 + 2 * k);
+    drho += s[k];
+    if constexpr (v.x > 0) j[0] += d[k];
+    if constexpr (v.x < 0) j[0] -= d[k];
+    if constexpr (v.y > 0) j[1] += d[k];
+    if constexpr (v.y < 0) j[1] -= d[k];
+    if constexpr (v.z > 0) j[2] += d[k];
+    if constexpr (v.z < 0) j[2] -= d[k];
+    if constexpr (v.x != 0) P[0] += s[k];
+    if constexpr (v.y != 0) P[1] += s[k];
+    if constexpr (v.z != 0) P[2] += s[k];
+    if constexpr (v.x * v.y > 0) P[3] += s[k];
+    if constexpr (v.x * v.y < 0) P[3] -= s[k];
+    if constexpr (v.x * v.z > 0) P[4] += s[k];
+    if constexpr (v.x * v.z < 0) P[4] -= s[k];
+    if constexpr (v.y * v.z > 0) P[5] += s[k];
+    if constexpr (v.y * v.z < 0) P[5] -= s[k];
+  });
+}
+
+// Moments from the deviations h_i.
+template <class L, class R>
+__device__ __forceinline__ void raw_moments(const R h[L::Q], R& drho, R j[3], R P[6]) {
+  constexpr int H = (L::Q - 1) / 2;
+  R s[H], d[H];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    const Dir v = L::dir(i);
-    drho += h[i];
-    if (v.x) j[0] += (R)v.x * h[i];
-    if (v.y) j[1] += (R)v.y * h[i];
-    if (L::D == 3 && v.z) j[2] += (R)v.z * h[i];
-    if (v.x) P[0] += h[i];
-    if (v.y) P[1] += h[i];
-    if (L::D == 3 && v.z) P[2] += h[i];
-    if (v.x * v.y) P[3] += (R)(v.x * v.y) * h[i];
-    if (L::D == 3 && v.x * v.z) P[4] += (R)(v.x * v.z) * h[i];
-    if (L::D == 3 && v.y * v.z) P[5] += (R)(v.y * v.z) * h[i];
+  for (int k = 0; k < H; ++k) {
+    s[k] = h[1 + 2 * k] + h[2 + 2 * k];
+    d[k] = h[1 + 2 * k] - h[2 + 2 * k];
   }
+  pair_moments<L, R>(h[0], s, d, drho, j, P);
+}
+
+// Moments from stored values: shifted formats store h; the plain formats
+// store f, and a pair's shift 2 w rho0 is removed from its sum only.
+template <class L, class S>
+__device__ __forceinline__ void stored_moments(const typename S::T raw[L::Q],
+                                               typename S::R rho0, typename S::R& drho,
+                                               typename S::R j[3], typename S::R P[6]) {
+  using R = typename S::R;
+  constexpr int H = (L::Q - 1) / 2;
+  R s[H], d[H];
+  static_for<0, H>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const R a = (R)raw[1 + 2 * k], b = (R)raw[2 + 2 * k];
+    if constexpr (S::kShifted)
+      s[k] = a + b;
+    else
+      s[k] = (a + b) - (R)(2.0 * L::w(1 + 2 * k)) * rho0;
+    d[k] = a - b;
+  });
+  const R h0 = S::kShifted ? (R)raw[0] : (R)raw[0] - (R)L::w(0) * rho0;
+  pair_moments<L, R>(h0, s, d, drho, j, P);
+}
+
+// 1 / x: hardware reciprocal in FP32 (one ulp), exact division in FP64
+template <class R>
+__device__ __forceinline__ R recip(R x) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_amdgcn_rcpf(x);
+  else
+    return (R)1 / x;
 }
 
 // a2_neq = Pi - rho cs^2 I - rho u u from the deviation moments
@@ -300,22 +400,19 @@ struct CellMoments {
 // deviations; out: post-collision deviations.  Returns rho* for the
 // stability watchdog; fills *mo when given.
 template <class L, class R, bool kSponge>
-__device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
-                                     R rho_ref, const R uref[3], R out[L::Q],
-                                     CellMoments<R>* mo = nullptr) {
-  constexpr int Q = L::Q;
-  R drho, j[3], P[6];
-  raw_moments<L, R>(h, drho, j, P);
+__device__ __forceinline__ R collide_moments(R drho, R j[3], const R P[6], R omega1, R rho0,
+                                             R chi, R rho_ref, const R uref[3], R base,
+                                             R out[L::Q], CellMoments<R>* mo = nullptr) {
   if constexpr (kSponge) {
     if (chi != (R)0) {
-      const R k = (R)1 / ((R)1 + (R)0.5 * chi);
+      const R k = recip((R)1 + (R)0.5 * chi);
       drho = (drho + (R)0.5 * chi * (rho_ref - rho0)) * k;
 #pragma unroll
       for (int a = 0; a < 3; ++a) j[a] = (j[a] + (R)0.5 * chi * rho_ref * uref[a]) * k;
     }
   }
   const R rho = rho0 + drho;
-  const R irho = (R)1 / rho;
+  const R irho = recip(rho);
   R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
   // a2_neq = Pi - rho cs^2 I - rho u u  (Pi - rho0 cs^2 I = P)
   R a2[6];
@@ -364,9 +461,20 @@ __device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi,
   }
   R bk[L::K];
   basis_coeffs<L, R>(c.m3, bk);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) out[i] = rebuild_one<L, R>(c, bk, i);
+  rebuild_all<L, R>(c, bk, base, out);
   return rho;
+}
+
+// Collision of one cell from its pre-collision deviations h; out receives
+// post-collision deviations.
+template <class L, class R, bool kSponge>
+__device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi, R rho_ref,
+                                     const R uref[3], R out[L::Q],
+                                     CellMoments<R>* mo = nullptr) {
+  R drho, j[3], P[6];
+  raw_moments<L, R>(h, drho, j, P);
+  return collide_moments<L, R, kSponge>(drho, j, P, omega1, rho0, chi, rho_ref, uref, (R)0,
+                                        out, mo);
 }
 
 // Deviations of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u) (initial state and
@@ -394,8 +502,7 @@ __device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
   for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
   R bk[L::K];
   basis_coeffs<L, R>(c.m3, bk);
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) out[i] = rebuild_one<L, R>(c, bk, i);
+  rebuild_all<L, R>(c, bk, (R)0, out);
 }
 
 // ------------------------------------------------------------------------

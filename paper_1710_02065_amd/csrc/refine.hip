@@ -65,8 +65,9 @@ int validate_refinement(const lbm_config& c) {
       return set_error(LBM_EINVAL, "refinement box axis %d overlaps an absorbing layer", a);
     fcells *= 2 * (hi - lo) + 1;
   }
-  if (fcells > 2147483647LL)
-    return set_error(LBM_EINVAL, "fine level has %lld cells; the limit is 2^31 - 1",
+  if (fcells > 2147483647LL ||
+      (double)pop_stride((uint64_t)fcells) * (double)storage_bytes(c.storage) > 4294967040.0)
+    return set_error(LBM_EINVAL, "fine level has %lld cells: above the per-level limit",
                      (long long)fcells);
   return LBM_OK;
 }

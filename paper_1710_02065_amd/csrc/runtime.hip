@@ -101,6 +101,11 @@ int validate(const lbm_config* cfg) {
   const double cells = (double)c.nx * (double)c.ny * (double)c.nz;
   if (cells > 2147483647.0)
     return set_error(LBM_EINVAL, "grid has %.0f cells; the limit is 2^31 - 1", cells);
+  // each population array is addressed with 32-bit byte offsets
+  if ((double)pop_stride((uint64_t)cells) * (double)storage_bytes(c.storage) > 4294967040.0)
+    return set_error(LBM_EINVAL,
+                     "grid has %.0f cells: one population array would exceed 4 GiB "
+                     "(limit 2^31 cells for F16S, 2^30 for F32/F32S, 2^29 for F64)", cells);
   if (!(c.tau > 0.5) || !std::isfinite(c.tau))
     return set_error(LBM_EINVAL, "tau = %g: nu = cs^2 (tau - 1/2) must be > 0", c.tau);
   if (!(c.rho0 > 0)) return set_error(LBM_EINVAL, "rho0 must be > 0");

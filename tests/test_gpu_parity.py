@@ -306,3 +306,24 @@ def test_full_size_channel_one_step():
     g.t = 5
     g.step(1)
     assert normwise(f1, g.f) <= TOL["f32"]
+
+
+def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
+    from paper_1710_02065_amd import lbm
+    monkeypatch.setenv("HRLBM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    case = dict(name="tune", q=19, shape=(48, 40, 36), tau=0.55)
+    rho, u, p = W.random_state(case["shape"], seed=13, d=3)
+    log("autotune")
+    a = gpu_sim(case, "f32").init(rho, u, p).step(3)
+    f0 = a.populations().cpu().numpy()
+    best = lbm.lbm_autotune(a.ctx, 1)
+    assert best in (64, 128, 256, 512, 1024)
+    np.testing.assert_array_equal(a.populations().cpu().numpy(), f0)
+    a.step(4)
+    b = gpu_sim(case, "f32", block=64).init(rho, u, p).step(7)
+    np.testing.assert_array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    text = (tmp_path / "tune.json").read_text()
+    assert ": %d" % best in text
+    c = gpu_sim(case, "f32").init(rho, u, p)  # picks the cached size
+    c.step(7)
+    np.testing.assert_array_equal(c.populations().cpu().numpy(), b.populations().cpu().numpy())

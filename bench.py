@@ -121,6 +121,103 @@ def cpu_baseline(n, seconds):
                        "(%.1f s) after initialisation" % (n, steps, dt))
 
 
+def precision_study(lbm, torch, n, fields, horizons):
+    """FP32, FP32-shifted and FP16-shifted storage run side by side with the
+    FP64 build (which matches the oracle to 1e-12) on the headline workload;
+    relative L2 error of the acoustic pressure p' = cs^2 (rho - rho0) and of
+    u at each horizon."""
+    sims = {}
+    for st in ("f64", "f32", "f32s", "f16s"):
+        sims[st] = lbm.Simulation(lattice=19, shape=(n, n, n), tau=0.52, storage=st)
+        sims[st].init(*fields)
+    out = {}
+    done = 0
+    for T in horizons:
+        for sim in sims.values():
+            sim.step(T - done)
+        done = T
+        r64, u64 = sims["f64"].moments()
+        p64 = (r64 - 1.0) / 3.0
+        row = {}
+        for st in ("f32", "f32s", "f16s"):
+            r, u = sims[st].moments()
+            row[st] = dict(p_rel_l2=float((((r - 1.0) / 3.0 - p64).norm() / p64.norm()).item()),
+                           u_rel_l2=float(((u - u64).norm() / u64.norm()).item()))
+        out[str(T)] = row
+    for sim in sims.values():
+        sim.sync()
+    del sims
+    torch.cuda.empty_cache()
+    return out
+
+
+def time_steps(sim, torch, steps):
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    sim.step(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sim.sync()
+    return a.elapsed_time(b)
+
+
+def other_configs(lbm, torch, steps):
+    """Full-size runs of the other single-GPU configurations (not the
+    headline): the D2Q9 cylinder channel and the D3Q27 jet with a 2:1 block."""
+    from paper_1710_02065_amd import workloads as W
+    res = {}
+    # D2Q9 2048 x 1024 channel, cylinder D = 100 at (400, 512), Ma 0.2, Re 150
+    nx, ny, D = 2048, 1024, 100
+    U = 0.2 * math.sqrt(1.0 / 3.0)
+    sim = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150, storage="f32",
+                         ma=0.2, face_bc=(2, 2, 1, 1, 0, 0), sponge_width=(0, 128, 0, 0, 0, 0),
+                         chi_max=0.2, rho_ref=1.0, u_ref=(U, 0, 0), seed=2)
+    rho, u = W.uniform_perturbed((nx, ny, 1), U, (1, 0, 0), seed=2, rel_noise=1e-4, d=2)
+    sim.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
+    sim.step(64)
+    sim.block = lbm.lbm_autotune(sim.ctx, 2)
+    ms = time_steps(sim, torch, steps)
+    N = nx * ny
+    bytes_lup = 2 * 9 * 4 + 1
+    res["d2q9_cylinder_2048x1024_f32"] = dict(
+        mlups=round(N * steps / (ms * 1e3), 1), steps=steps, workgroup=sim.block,
+        hbm_gbs=round(bytes_lup * N * steps / (ms / 1e3) / 1e9, 1),
+        note="72 B/LUP populations + 1 B mask; 151 MB of state fits the 256 MB MALL")
+    del sim
+    torch.cuda.empty_cache()
+    # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
+    # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]
+    shape = (384, 256, 256)
+    Uj = 0.3 * math.sqrt(1.0 / 3.0)
+    nu = Uj * 20 / 3600
+    tau = 0.5 + 3 * nu
+    lo, hi = (4, 64, 64), (196, 191, 191)
+    sim = lbm.Simulation(lattice=27, shape=shape, tau=tau, storage="f32", ma=0.3,
+                         face_bc=(2, 2, 2, 2, 2, 2), sponge_width=(0, 64, 64, 64, 64, 64),
+                         chi_max=0.2, rho_ref=1.0, seed=4, inlet_noise=0.02,
+                         refine_lo=lo, refine_hi=hi)
+    sim.init(None, torch.zeros(3, shape[0] * shape[1] * shape[2], dtype=torch.float64,
+                               device="cuda"), None, W.jet_inlet_mask(*shape, D=20), level=0)
+    fs = sim.shape(1)
+    sim.init(None, torch.zeros(3, fs[0] * fs[1] * fs[2], dtype=torch.float64, device="cuda"),
+             level=1)
+    sim.step(8)
+    js = max(steps // 10, 20)
+    ms = time_steps(sim, torch, js)
+    ups = sim.updates_per_step
+    res["d3q27_jet_384x256x256_refined_f32"] = dict(
+        mlups=round(ups * js / (ms * 1e3), 1), coarse_steps=js, updates_per_coarse_step=ups,
+        hbm_gbs=round(2 * 27 * 4 * ups * js / (ms / 1e3) / 1e9, 1),
+        note="updates = swept coarse cells + 2 x swept fine cells per coarse step; "
+             "refined block starts 4 cells from the inlet face (coupling margin)")
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_bench(n_jobs, step_scale, load, budget_gib, quantum):
     """Continuous-batching serving of the D2Q9 job mix: first all jobs at
     t = 0 (saturated throughput), then a seeded Poisson stream offered at
@@ -159,6 +256,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--config-steps", type=int, default=500)
+    ap.add_argument("--precision-horizons", type=lambda s: [int(x) for x in s.split(",")],
+                    default=[500, 1000, 2000, 5000])
     ap.add_argument("--serve-jobs", type=int, default=48)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -203,31 +304,27 @@ def main():
     mlups32 = N * args.steps / (ms32 * 1e3)
     bytes_lup = 2 * 19 * 4
     per_launch_s = ms32 / 1e3 / args.steps
+    wg32 = sim32.block
     achieved = bytes_lup * N / per_launch_s / 1e9
     traffic = measured_traffic("k_sweep_d3q19_f32_256") if n == 256 else None
 
     variants = {}
     precision = {}
+    del sim32
+    torch.cuda.empty_cache()
     if not args.no_variants:
-        log("timing f16s")
-        sim16, ms16 = run_gpu(lbm, torch, "f16s", n, args.steps, args.warmup, fields, args.block)
-        mlups16 = N * args.steps / (ms16 * 1e3)
-        variants["f16s"] = dict(
-            value=round(mlups16, 1), unit="MLUPS", bytes_per_lup=2 * 19 * 2,
-            hbm_gbs=round(2 * 19 * 2 * N / (ms16 / 1e3 / args.steps) / 1e9, 1),
-            speedup_vs_f32=round(mlups16 / mlups32, 3))
-        log("precision reference: f64 build, %d steps" % (args.warmup + args.steps))
-        sim64, ms64 = run_gpu(lbm, torch, "f64", n, args.steps, args.warmup, fields, args.block)
-        variants["f64"] = dict(value=round(N * args.steps / (ms64 * 1e3), 1), unit="MLUPS")
-        r64, u64 = sim64.moments()
-        for name, sim in (("f32", sim32), ("f16s", sim16)):
-            perr, r, u = pressure_error(sim, r64)
-            precision[name] = dict(
-                horizon_steps=args.warmup + args.steps,
-                acoustic_pressure_rel_l2=perr,
-                rho_max_abs=float((r - r64).abs().max().item()),
-                u_rel_l2=float(((u - u64).norm() / u64.norm()).item()))
-        del sim64, sim16, r64, u64
+        for st in ("f16s", "f32s", "f64"):
+            log("timing %s" % st)
+            sv, msv = run_gpu(lbm, torch, st, n, args.steps, args.warmup, fields, args.block)
+            b = 2 * 19 * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
+            mv = N * args.steps / (msv * 1e3)
+            variants[st] = dict(value=round(mv, 1), unit="MLUPS", bytes_per_lup=b,
+                                hbm_gbs=round(b * N / (msv / 1e3 / args.steps) / 1e9, 1),
+                                speedup_vs_f32=round(mv / mlups32, 3), workgroup=sv.block)
+            del sv
+            torch.cuda.empty_cache()
+        log("precision study: f64 / f32 / f32s / f16s side by side")
+        precision = precision_study(lbm, torch, n, fields, args.precision_horizons)
 
     out = {
         "metric": METRIC,
@@ -246,7 +343,7 @@ def main():
             "workload": "D3Q19 %d^3 periodic, Taylor-Green U=0.1cs + Gaussian pulse 1e-3 "
                         "sigma 8, tau 0.52, FP32 storage (fused pull + rrBGK sweep)" % n,
             "lattice": "D3Q19", "cells": N, "storage": "f32", "tau": 0.52,
-            "workgroup": sim32.block, "parallelism": "single GPU"},
+            "parallelism": "single GPU"},
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -258,8 +355,11 @@ def main():
         out["variants"] = variants
     if precision:
         out["precision_vs_f64_build"] = precision
-    del sim32
-    torch.cuda.empty_cache()
+    out["config"]["workgroup"] = wg32
+    if not args.no_configs:
+        log("other configurations")
+        out["configs"] = other_configs(lbm, torch, args.config_steps)
+        torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving: %d jobs, step scale %g" % (args.serve_jobs, args.serve_step_scale))
         out["serving"] = serving_bench(args.serve_jobs, args.serve_step_scale, args.serve_load,

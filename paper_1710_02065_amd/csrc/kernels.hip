@@ -66,7 +66,7 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
       }
     }
     const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
-    if (a.mask && a.mask[src] == kSolid) {
+    if (a.mask && (a.mask[src] & kKindBits) == kSolid) {
       // halfway bounce-back: the population that left this cell towards
       // the wall comes back reversed (same weight, so the same shift)
       constexpr int o = opposite<L>(i);
@@ -78,6 +78,38 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
                         flip[2] ? -v.z : v.z);
       raw[i] = load_pop(a.src + (uint64_t)pop * P, src);
     }
+  });
+}
+
+// Pull of all populations of a cell whose neighbours need no face rule or
+// bounce-back: offsets to the x-1 / x+1 (etc.) neighbours, with wrap-around
+// on periodic axes.
+template <class L, class S>
+__device__ __forceinline__ void pull_periodic(const SweepArgs<S>& a, uint32_t c, uint32_t x,
+                                              uint32_t y, uint32_t z,
+                                              typename S::T raw[L::Q]) {
+  const uint64_t P = a.pstride;
+  const int32_t nx = (int32_t)a.nx, nxy = (int32_t)(a.nx * a.ny);
+  const int32_t ox_m = x == 0 ? nx - 1 : -1;
+  const int32_t ox_p = x == a.nx - 1 ? -(nx - 1) : 1;
+  const int32_t oy_m = y == 0 ? (int32_t)(a.ny - 1) * nx : -nx;
+  const int32_t oy_p = y == a.ny - 1 ? -(int32_t)(a.ny - 1) * nx : nx;
+  int32_t oz_m = 0, oz_p = 0;
+  if constexpr (L::D == 3) {
+    oz_m = z == 0 ? (int32_t)(a.nz - 1) * nxy : -nxy;
+    oz_p = z == a.nz - 1 ? -(int32_t)(a.nz - 1) * nxy : nxy;
+  }
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr Dir v = L::dir(i);
+    int32_t off = 0;
+    if constexpr (v.x > 0) off += ox_m;
+    if constexpr (v.x < 0) off += ox_p;
+    if constexpr (v.y > 0) off += oy_m;
+    if constexpr (v.y < 0) off += oy_p;
+    if constexpr (v.z > 0) off += oz_m;
+    if constexpr (v.z < 0) off += oz_p;
+    raw[i] = load_pop(a.src + (uint64_t)i * P, (uint32_t)((int32_t)c + off));
   });
 }
 
@@ -102,37 +134,15 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   R post[Q];
   R rho, drho, j[3], Pm[6];
   if constexpr (!kGeneral) {
-    // periodic wrap: offsets to the x-1 / x+1 (etc.) neighbours
-    const int32_t nx = (int32_t)a.nx, nxy = (int32_t)(a.nx * a.ny);
-    const int32_t ox_m = x == 0 ? nx - 1 : -1;
-    const int32_t ox_p = x == a.nx - 1 ? -(nx - 1) : 1;
-    const int32_t oy_m = y == 0 ? (int32_t)(a.ny - 1) * nx : -nx;
-    const int32_t oy_p = y == a.ny - 1 ? -(int32_t)(a.ny - 1) * nx : nx;
-    int32_t oz_m = 0, oz_p = 0;
-    if constexpr (L::D == 3) {
-      oz_m = z == 0 ? (int32_t)(a.nz - 1) * nxy : -nxy;
-      oz_p = z == a.nz - 1 ? -(int32_t)(a.nz - 1) * nxy : nxy;
-    }
-    static_for<0, Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      constexpr Dir v = L::dir(i);
-      int32_t off = 0;
-      if constexpr (v.x > 0) off += ox_m;
-      if constexpr (v.x < 0) off += ox_p;
-      if constexpr (v.y > 0) off += oy_m;
-      if constexpr (v.y < 0) off += oy_p;
-      if constexpr (v.z > 0) off += oz_m;
-      if constexpr (v.z < 0) off += oz_p;
-      raw[i] = load_pop(a.src + (uint64_t)i * P, (uint32_t)((int32_t)c + off));
-    });
+    pull_periodic<L, S>(a, c, x, y, z, raw);
     stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
     rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref,
                                        base, post);
   } else {
-    uint8_t m = kFluid;
-    if (a.mask) m = a.mask[c];
-    if (m == kSolid || m >= kCovered) return;
-    if (m == kInlet) {
+    const uint8_t m = a.mask ? a.mask[c] : kFluid;
+    const uint8_t kind = m & kKindBits;
+    if (kind == kSolid || kind >= kCovered) return;
+    if (kind == kInlet) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
       const uint64_t bidx =
@@ -152,15 +162,22 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       });
       return;
     }
-    pull_general<L, S>(a, x, y, z, c, raw);
+    if (!a.mask || (m & (kNearFace | kNearSolid)))
+      pull_general<L, S>(a, x, y, z, c, raw);
+    else
+      pull_periodic<L, S>(a, c, x, y, z, raw);
     stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
     R chi = (R)0;
     if (a.chi_max != (R)0)
       chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
     if (a.rec) {
       CellMoments<R> mo;
-      rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
-                                        base, post, &mo);
+      if (chi != (R)0)
+        rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
+                                          a.uref, base, post, &mo);
+      else
+        rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
+                                           a.uref, base, post, &mo);
       const int64_t r = record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z);
       if (r >= 0) {
         a.rec[r] = mo.drho;
@@ -169,9 +186,12 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
       }
-    } else {
+    } else if (chi != (R)0) {
       rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
                                         base, post);
+    } else {
+      rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
+                                         base, post);
     }
   }
   // stability watchdog: a rare, benign racy store of 1
@@ -239,7 +259,7 @@ __global__ void k_moments(MomentArgs a) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.ncell) return;
   const T* src = (const T*)a.src;
-  if (a.mask && (a.mask[c] == kSolid || a.mask[c] == kCovered)) {
+  if (a.mask && ((a.mask[c] & kKindBits) == kSolid || (a.mask[c] & kKindBits) == kCovered)) {
     if (a.rho_out) a.rho_out[c] = 0.0;
     if (a.u_out)
       for (int k = 0; k < 3; ++k) a.u_out[(uint64_t)k * a.ncell + c] = 0.0;
@@ -272,7 +292,7 @@ __global__ void k_probe(ProbeArgs a) {
     a.rho_out[n] = 0.0;
     return;
   }
-  if (a.mask && (a.mask[c] == kSolid || a.mask[c] == kCovered)) {
+  if (a.mask && ((a.mask[c] & kKindBits) == kSolid || (a.mask[c] & kKindBits) == kCovered)) {
     a.rho_out[n] = 0.0;
     return;
   }
@@ -365,6 +385,42 @@ __global__ void __launch_bounds__(1024) k_batch(const BatchJob* __restrict__ job
 
 __global__ void k_batch_bump(BatchHeader* hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->step += 1;
+}
+
+// Flag bits of every cell's mask byte: kNearSolid if a neighbour reached
+// by the pull is SOLID (after periodic wrap), kNearFace if the cell lies on a
+// face whose rule is not periodic.
+template <class L>
+__global__ void k_flags(FlagsArgs a) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = a.nx * a.ny * a.nz;
+  if (c >= n) return;
+  const int32_t p[3] = {(int32_t)(c % a.nx), (int32_t)((c / a.nx) % a.ny),
+                        (int32_t)(c / (a.nx * a.ny))};
+  const int32_t dims[3] = {(int32_t)a.nx, (int32_t)a.ny, (int32_t)a.nz};
+  uint8_t flags = 0;
+  for (int ax = 0; ax < L::D; ++ax)
+    if ((p[ax] == 0 && a.face[2 * ax] != kPeriodic) ||
+        (p[ax] == dims[ax] - 1 && a.face[2 * ax + 1] != kPeriodic))
+      flags |= kNearFace;
+  for (int i = 1; i < L::Q; ++i) {
+    const Dir v = L::dir(i);
+    int32_t s[3] = {p[0] - v.x, p[1] - v.y, p[2] - v.z};
+    bool inside = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      if (s[ax] < 0 || s[ax] >= dims[ax]) {
+        if (a.face[2 * ax] == kPeriodic)
+          s[ax] = (s[ax] + dims[ax]) % dims[ax];
+        else
+          inside = false;
+      }
+    }
+    if (inside &&
+        (a.mask[((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0]] & kKindBits) ==
+            kSolid)
+      flags |= kNearSolid;
+  }
+  a.mask[c] = (uint8_t)((a.mask[c] & kKindBits) | flags);
 }
 
 // ------------------------------------------------------------------------
@@ -701,6 +757,18 @@ int batch_grid(int lattice, int block) {
   }
   if (e != hipSuccess || per < 1) per = 1;
   return cus * per;
+}
+
+hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st) {
+  const uint32_t n = a.nx * a.ny * a.nz;
+  const uint32_t blocks = (n + 255) / 256;
+  switch (lattice) {
+    case 9: hipLaunchKernelGGL(k_flags<Lattice<9>>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 19: hipLaunchKernelGGL(k_flags<Lattice<19>>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 27: hipLaunchKernelGGL(k_flags<Lattice<27>>, dim3(blocks), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st) {

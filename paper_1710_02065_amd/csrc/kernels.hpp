@@ -29,6 +29,10 @@ enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
 // from fine data), RING (fine node rebuilt from coarse data); cells of the
 // three internal kinds are not swept.
 enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2, kCovered = 3, kImport = 4, kRing = 5 };
+// The mask byte holds the kind in its low six bits and two flags computed
+// at initialisation: the cell has a SOLID neighbour, or it lies on a
+// non-periodic face.  Cells with neither flag pull like a periodic grid.
+enum : uint8_t { kKindBits = 0x3F, kNearFace = 0x40, kNearSolid = 0x80 };
 
 // ------------------------------------------------------------------------
 // Division of 32-bit unsigned numbers below 2^31 by a run-time invariant

@@ -40,6 +40,14 @@ struct RolesArgs {
   int32_t lo[3], hi[3];
 };
 
+// Flag bits of the mask (see kernels.hpp): near a SOLID cell, on a
+// non-periodic face.
+struct FlagsArgs {
+  uint8_t* mask;
+  uint32_t nx, ny, nz;
+  int32_t face[6];
+};
+
 // Record box of the coarse moments filled from the initial fields.
 struct RecordFieldsArgs {
   const double* rho;
@@ -168,6 +176,7 @@ hipError_t launch_get_pop(int lattice, int storage, const PopArgs& a,
 hipError_t launch_set_pop(int lattice, int storage, const PopArgs& a,
                           uint32_t n, hipStream_t st);
 hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st);
+hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st);
 hipError_t launch_record_fields(int lattice, int storage, const RecordFieldsArgs& a,
                                 uint32_t n, hipStream_t st);
 hipError_t launch_ring(int lattice, int storage, const RingArgs& a, uint32_t n,

@@ -468,10 +468,25 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   for (int k = 0; k < 3; ++k) a.uin[k] = ctx->uin[k];
   e = launch_init(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "init launch");
-  L.has_mask = mask != nullptr;
+  // any level that is not a fully periodic, sponge-free, unrefined grid
+  // keeps a mask (all FLUID if none was given) with the flag bits
+  bool general = mask != nullptr || ctx->nlevels > 1 || L.chi_max > 0;
+  for (int f = 0; f < 6; ++f)
+    if (L.face[f] != LBM_PERIODIC) general = true;
+  L.has_mask = general;
   if (ctx->nlevels > 1) {
     rc = refined_init_level(ctx, level, rho, u, pi_neq);
     if (rc != LBM_OK) return rc;
+  }
+  if (general) {
+    FlagsArgs fa{};
+    fa.mask = L.mask;
+    fa.nx = (uint32_t)L.nx;
+    fa.ny = (uint32_t)L.ny;
+    fa.nz = (uint32_t)L.nz;
+    for (int f = 0; f < 6; ++f) fa.face[f] = L.face[f];
+    e = launch_flags(ctx->cfg.lattice, fa, ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "flags launch");
   }
   if (mask) {
     // inlet cells draw noise: note whether any exist (host scan of a copy)

@@ -441,14 +441,14 @@ static int ora_mirror(const ora_lattice* L, int i, int axis) {
   return -1;
 }
 
-/* Pre-collision population i at cell (x, y, z), pulled from the
- * post-collision field fin (left side of eq. optimizedLB read backwards):
- * the source is x - xi_i, mapped through the face rules axis by axis, and a
- * link whose source is a SOLID cell is bounced back halfway. */
-static double ora_pull(const ora_grid* g, const ora_lattice* L,
-                       const uint8_t* mask, const double* fin, int64_t x,
-                       int64_t y, int64_t z, int i) {
-  int64_t N = g->nx * g->ny * g->nz;
+/* Source of population i pulled into cell (x, y, z): the cell x - xi_i,
+ * mapped through the face rules axis by axis (periodic wrap; free-slip:
+ * reflected back to the boundary row with the population mirrored;
+ * outflow: the boundary row).  Returns 1 if that source is SOLID (the link
+ * is bounced back), else 0 with *src_cell and *src_pop set. */
+static int ora_source(const ora_grid* g, const ora_lattice* L,
+                      const uint8_t* mask, int64_t x, int64_t y, int64_t z,
+                      int i, int64_t* src_cell, int* src_pop) {
   int64_t s[3] = {x - L->xi[i][0], y - L->xi[i][1], z - L->xi[i][2]};
   int64_t dims[3] = {g->nx, g->ny, g->nz};
   int si = i, a;
@@ -470,9 +470,23 @@ static double ora_pull(const ora_grid* g, const ora_lattice* L,
         break;
     }
   }
-  if (mask && mask[ora_cell(g, s[0], s[1], s[2])] == ORA_SOLID)
+  *src_cell = ora_cell(g, s[0], s[1], s[2]);
+  *src_pop = si;
+  return mask && mask[*src_cell] == ORA_SOLID;
+}
+
+/* Pre-collision population i at cell (x, y, z), pulled from the
+ * post-collision field fin (left side of eq. optimizedLB read backwards); a
+ * link whose source is a SOLID cell is bounced back halfway: the population
+ * that left this cell towards the wall returns reversed. */
+static double ora_pull(const ora_grid* g, const ora_lattice* L,
+                       const uint8_t* mask, const double* fin, int64_t x,
+                       int64_t y, int64_t z, int i) {
+  int64_t N = g->nx * g->ny * g->nz, sc;
+  int sp;
+  if (ora_source(g, L, mask, x, y, z, i, &sc, &sp))
     return fin[(int64_t)L->opp[i] * N + ora_cell(g, x, y, z)];
-  return fin[(int64_t)si * N + ora_cell(g, s[0], s[1], s[2])];
+  return fin[(int64_t)sp * N + sc];
 }
 
 /* Inlet velocity at a cell for the state being produced at time index t:
@@ -568,6 +582,36 @@ void ora_step_ex(const ora_grid* g, const uint8_t* mask, const uint8_t* skip,
 void ora_step(const ora_grid* g, const uint8_t* mask, const double* fin,
               double* fout, int64_t t_new) {
   ora_step_ex(g, mask, NULL, fin, fout, t_new, NULL, NULL, NULL);
+}
+
+/* Force on all SOLID cells by momentum exchange (Ladd 1994; Mei, Yu, Shyy &
+ * Luo 2002), from the post-collision state f at one time level: on every
+ * bounced-back link of a FLUID cell x, the population f*_j(x) travelling
+ * into the wall (xi_j = -xi_i for the pulled direction i) returns reversed
+ * at the next step, so the wall receives 2 f*_j(x) xi_j.  F[3] receives the
+ * sum over cells in index order and directions in lattice order. */
+void ora_force(const ora_grid* g, const uint8_t* mask, const double* f,
+               double* F) {
+  ora_lattice L;
+  int64_t N = g->nx * g->ny * g->nz, x, y, z;
+  int a;
+  F[0] = F[1] = F[2] = 0.0;
+  if (!mask || ora_make_lattice(g->lattice, &L)) return;
+  for (z = 0; z < g->nz; ++z)
+    for (y = 0; y < g->ny; ++y)
+      for (x = 0; x < g->nx; ++x) {
+        int64_t c = ora_cell(g, x, y, z), sc;
+        int i, sp;
+        if (mask[c] != ORA_FLUID) continue;
+        for (i = 1; i < L.q; ++i) {
+          if (!ora_source(g, &L, mask, x, y, z, i, &sc, &sp)) continue;
+          {
+            int j = L.opp[i];
+            double fj = f[(int64_t)j * N + c];
+            for (a = 0; a < 3; ++a) F[a] += 2.0 * fj * L.xi[j][a];
+          }
+        }
+      }
 }
 
 /* Density and velocity of the stored post-collision state at each cell:

@@ -39,6 +39,7 @@ def lib():
         L.ora_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, C.c_int64]
         L.ora_moments.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp]
         L.ora_sizeof_grid.restype = C.c_int
+        L.ora_force.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
         L.ora_step_ex.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp, dp, C.c_int64,
                                   dp, dp, dp]
         L.ora_sizeof_refined.restype = C.c_int
@@ -193,6 +194,12 @@ class Grid:
 
     def chi(self, x, y, z=0):
         return lib().ora_sponge_chi(C.byref(self.g), x, y, z)
+
+    def force(self):
+        """Momentum-exchange force on the SOLID cells (3 components)."""
+        F = np.zeros(3)
+        lib().ora_force(C.byref(self.g), self._mask_ptr, _dp(self.f), _dp(F))
+        return F
 
 
 class OraRefined(C.Structure):

@@ -242,3 +242,82 @@ def test_inlet_noise_contract():
             r = (O.splitmix64(seed, k) >> 40) * 2.0 ** -23 - 1.0
             assert u[a][c] == pytest.approx(ua * (1 + noise * r), abs=1e-15)
         assert rho[c] == pytest.approx(1.0, abs=1e-15)
+
+
+def _block_mask(shape, lo, hi):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    inside = np.ones(x.shape, bool)
+    for p, a, b in zip((x, y, z), lo, hi):
+        inside &= (p >= a) & (p < b)
+    return np.where(inside.ravel(), W.SOLID, W.FLUID).astype(np.uint8)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (40, 30, 1)), (19, (16, 14, 12)), (27, (14, 12, 12))])
+def test_force_equals_fluid_momentum_loss(q, shape):
+    """Momentum balance of a periodic domain with an obstacle: nothing but
+    the wall exchanges momentum with the fluid (the collision conserves it),
+    so the momentum-exchange force of the state at t equals the fluid's
+    momentum at t minus that at t+1, exactly up to rounding."""
+    d = 2 if q == 9 else 3
+    lo = (5, 6, 3)[:d] + (0,) * (3 - d)
+    hi = (11, 13, 8)[:d] + (1,) * (3 - d)
+    mask = _block_mask(shape, lo, hi)
+    rho, u, p = W.random_state(shape, seed=21, d=d, u_amp=0.03)
+    u[0] += 0.05
+    u[:, mask == W.SOLID] = 0.0
+    g = O.Grid(q, *shape, tau=0.65, mask=mask).init(rho, u, p)
+    g.step(20)
+    xi, _, _ = O.lattice(q)
+    fluid = mask == W.FLUID
+
+    def momentum():
+        return (g.f[:, fluid].sum(axis=1)[:, None] * xi).sum(axis=0)
+
+    F = g.force()
+    j0 = momentum()
+    scale = np.abs(g.f[:, fluid]).sum()  # the sums' rounding grows with it
+    g.step(1)
+    j1 = momentum()
+    assert np.abs(F).max() > 1e-3
+    np.testing.assert_allclose(F, j0 - j1, rtol=0, atol=64 * np.finfo(float).eps * scale)
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_force_at_rest_is_pressure_times_area(q):
+    """A fluid at rest at density rho0 on a flat solid floor pushes it down
+    with p A = rho0 cs^2 A (A = wall cells), whatever the lattice: the
+    weights of the directions pointing into the wall sum to 1/6."""
+    shape = (12, 10, 1) if q == 9 else (6, 8, 5)
+    nx, ny, nz = shape
+    mask = _block_mask(shape, (0, 0, 0), (nx, 2, nz))
+    rho0 = 1.3
+    N = nx * ny * nz
+    face = (O.PERIODIC, O.PERIODIC, O.FREESLIP, O.FREESLIP, O.PERIODIC, O.PERIODIC)
+    g = O.Grid(q, *shape, tau=0.7, rho0=rho0, face_bc=face, mask=mask)
+    g.init(np.full(N, rho0), np.zeros((3, N)))
+    g.step(3)
+    F = g.force()
+    assert F[1] == pytest.approx(-rho0 * CS2 * nx * nz, rel=1e-13)
+    assert abs(F[0]) < 1e-13 and abs(F[2]) < 1e-13
+
+
+def test_force_symmetric_body_drag_without_lift():
+    """Impulsively started flow along x past a body symmetric about the
+    domain's mid line: the drag, averaged over the acoustic transient, points
+    downstream and the lift vanishes to rounding at every step."""
+    shape = (48, 24, 1)
+    mask = _block_mask(shape, (10, 9, 0), (15, 15, 1))
+    N = 48 * 24
+    u = np.zeros((3, N))
+    u[0] = 0.05
+    u[:, mask == W.SOLID] = 0.0
+    g = O.Grid(9, *shape, tau=0.6, mask=mask).init(np.ones(N), u)
+    Fs = []
+    for _ in range(200):
+        g.step(1)
+        Fs.append(g.force())
+    Fs = np.array(Fs)
+    assert Fs[:, 0].mean() > 0.01
+    assert np.abs(Fs[:, 1]).max() < 1e-12 * np.abs(Fs[:, 0]).max()
+    assert np.all(Fs[:, 2] == 0.0)

@@ -191,6 +191,30 @@ int lbm_moments(lbm_ctx* ctx, int level, double* rho_out, double* u_out);
 int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n,
               double* rho_out);
 
+/* Running field statistics for the fluctuating pressure of Sec. III (the
+ * pressure minus its temporal mean, p = cs^2 rho): adds x = rho - rho0 of
+ * the current stored state to sum1[c] and x*x to sum2[c] for every cell c of
+ * `level` (SOLID and COVERED cells add 0).  sum1, sum2: caller-owned FP64
+ * device arrays of N entries, zeroed by the caller before the first call;
+ * either may be NULL.  Enqueued on the context's stream; calls on one
+ * context accumulate in order.  After n calls the temporal mean of p is
+ * cs^2 (rho0 + sum1/n) and the rms of its fluctuation
+ * cs^2 sqrt(sum2/n - (sum1/n)^2). */
+int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2);
+
+/* Force on all SOLID cells of `level` by momentum exchange (Ladd 1994; Mei,
+ * Yu, Shyy & Luo 2002), the body force behind the drag and lift of the
+ * cylinder flow of Sec. III: on every link of a FLUID cell whose pulled
+ * source (under the face rules) is SOLID, the stored post-collision
+ * population f*_j moving into the wall returns reversed at the next step,
+ * so the wall receives 2 f*_j xi_j.  out: FP64 device pointer to 3
+ * components (x, y, z; z = 0 in 2D), written on the context's stream, in
+ * lattice units per step.  Uses a reduction area inside the context's
+ * memory, so two calls on one context must not overlap on different
+ * streams.  The summation order is fixed: repeated calls give identical
+ * bits.  A context without a mask gives 0. */
+int lbm_force(lbm_ctx* ctx, int level, double* out);
+
 /* Canonical FP64 copy of the stored populations of `level`, [q][N] in the
  * documented direction order, unshifted (device pointers).  Used for
  * checkpoint/resume and parity checks.  set also resets nothing else:

@@ -281,6 +281,28 @@ __global__ void k_moments(MomentArgs a) {
     for (int k = 0; k < 3; ++k) a.u_out[(uint64_t)k * a.ncell + c] = (double)j[k] / rho;
 }
 
+// Running sums of the density deviation x = rho - rho0 of the stored state
+// and of its square, for temporal means and rms fluctuations (SOLID and
+// COVERED cells add 0).
+template <class L, class S>
+__global__ void k_accum(AccumArgs a) {
+  using R = typename S::R;
+  using T = typename S::T;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.ncell) return;
+  if (a.mask && ((a.mask[c] & kKindBits) == kSolid || (a.mask[c] & kKindBits) == kCovered))
+    return;
+  const T* src = (const T*)a.src;
+  R drho = (R)0;
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    drho += decode<S>(src[(uint64_t)i * a.pstride + c], (R)L::w(i) * (R)a.rho0);
+  });
+  const double x = (double)drho;
+  if (a.sum1) a.sum1[c] += x;
+  if (a.sum2) a.sum2[c] += x * x;
+}
+
 template <class L, class S>
 __global__ void k_probe(ProbeArgs a) {
   using R = typename S::R;
@@ -303,6 +325,84 @@ __global__ void k_probe(ProbeArgs a) {
     drho += decode<S>(src[(uint64_t)i * a.pstride + c], (R)L::w(i) * (R)a.rho0);
   });
   a.rho_out[n] = a.rho0 + (double)drho;
+}
+
+// ------------------------------------------------------------------------
+// Force on the SOLID cells by momentum exchange (Ladd; Mei et al. 2002):
+// for every link of a FLUID cell whose pulled source (under the face rules,
+// as in pull_general) is SOLID, the post-collision population f*_j moving
+// into the wall (xi_j = -xi_i) returns reversed, so the wall receives
+// 2 f*_j xi_j.  Stage one: a fixed grid of kForceBlocks walks the cells
+// with a fixed stride and reduces in a fixed LDS tree into one partial per
+// block; stage two sums the partials in a fixed tree.  The result does not
+// depend on scheduling.
+// ------------------------------------------------------------------------
+template <class L, class S>
+__global__ void __launch_bounds__(kForceThreads) k_force(ForceArgs a) {
+  using T = typename S::T;
+  __shared__ double red[3][kForceThreads];
+  double F[3] = {0.0, 0.0, 0.0};
+  const uint32_t n = a.nx * a.ny * a.nz;
+  const T* src = (const T*)a.src;
+  const int32_t dims[3] = {(int32_t)a.nx, (int32_t)a.ny, (int32_t)a.nz};
+  if (a.mask) {
+    for (uint32_t c = blockIdx.x * kForceThreads + threadIdx.x; c < n;
+         c += kForceBlocks * kForceThreads) {
+      const uint8_t m = a.mask[c];
+      if ((m & kKindBits) != kFluid || !(m & (kNearSolid | kNearFace))) continue;
+      const int32_t p[3] = {(int32_t)(c % a.nx), (int32_t)((c / a.nx) % a.ny),
+                            (int32_t)(c / (a.nx * a.ny))};
+      static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr Dir v = L::dir(i);
+        int32_t s[3] = {p[0] - v.x, p[1] - v.y, p[2] - v.z};
+#pragma unroll
+        for (int ax = 0; ax < L::D; ++ax) {
+          if (s[ax] >= 0 && s[ax] < dims[ax]) continue;
+          const bool hi = s[ax] >= dims[ax];
+          if (a.face[2 * ax + (hi ? 1 : 0)] == kPeriodic)
+            s[ax] = hi ? s[ax] - dims[ax] : s[ax] + dims[ax];
+          else
+            s[ax] = hi ? dims[ax] - 1 : 0;
+        }
+        const uint32_t sc = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
+        if ((a.mask[sc] & kKindBits) == kSolid) {
+          constexpr int o = opposite<L>(i);
+          constexpr Dir w = L::dir(o);
+          const T raw = src[(uint64_t)o * a.pstride + c];
+          const double f = S::kShifted ? (double)raw + L::w(o) * a.rho0 : (double)raw;
+          if constexpr (w.x != 0) F[0] += 2.0 * w.x * f;
+          if constexpr (w.y != 0) F[1] += 2.0 * w.y * f;
+          if constexpr (w.z != 0) F[2] += 2.0 * w.z * f;
+        }
+      });
+    }
+  }
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = F[k];
+  __syncthreads();
+  for (uint32_t h = kForceThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) a.partial[(uint64_t)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kForceThreads) k_force_sum(ForceArgs a) {
+  __shared__ double red[3][kForceThreads];
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (uint32_t b = threadIdx.x; b < kForceBlocks; b += kForceThreads)
+      v += a.partial[(uint64_t)b * 3 + k];
+    red[k][threadIdx.x] = v;
+  }
+  __syncthreads();
+  for (uint32_t h = kForceThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) a.out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // canonical FP64 [q][N] <-> native storage
@@ -715,6 +815,7 @@ hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
 HRLBM_DISPATCH(init, InitArgs)
 HRLBM_DISPATCH(moments, MomentArgs)
 HRLBM_DISPATCH(probe, ProbeArgs)
+HRLBM_DISPATCH(accum, AccumArgs)
 HRLBM_DISPATCH(get_pop, PopArgs)
 HRLBM_DISPATCH(set_pop, PopArgs)
 HRLBM_DISPATCH(record_fields, RecordFieldsArgs)
@@ -768,6 +869,30 @@ hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st) {
     case 27: hipLaunchKernelGGL(k_flags<Lattice<27>>, dim3(blocks), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <class L>
+static void force_l(int storage, const ForceArgs& a, hipStream_t st) {
+  const dim3 g(kForceBlocks), b(kForceThreads);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL((k_force<L, StoreF64>), g, b, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_force<L, StoreF32>), g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_force<L, StoreF32S>), g, b, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_force<L, StoreF16S>), g, b, 0, st, a); break;
+  }
+}
+
+hipError_t launch_force(int lattice, int storage, const ForceArgs& a, hipStream_t st) {
+  switch (lattice) {
+    case 9: force_l<Lattice<9>>(storage, a, st); break;
+    case 19: force_l<Lattice<19>>(storage, a, st); break;
+    case 27: force_l<Lattice<27>>(storage, a, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_force_sum, dim3(1), dim3(kForceThreads), 0, st, a);
   return hipGetLastError();
 }
 

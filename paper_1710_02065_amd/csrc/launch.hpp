@@ -116,6 +116,16 @@ struct MomentArgs {
   double rho0;
 };
 
+struct AccumArgs {
+  const void* src;
+  const uint8_t* mask;
+  double* sum1;
+  double* sum2;
+  uint32_t ncell;
+  uint64_t pstride;
+  double rho0;
+};
+
 struct ProbeArgs {
   const void* src;
   const uint8_t* mask;
@@ -124,6 +134,20 @@ struct ProbeArgs {
   int n;
   uint32_t ncell;
   uint64_t pstride;
+  double rho0;
+};
+
+// Momentum-exchange force: kForceBlocks partial sums (3 doubles each) in
+// `partial`, the total in out[3].
+constexpr uint32_t kForceBlocks = 1024, kForceThreads = 256;
+struct ForceArgs {
+  const void* src;
+  const uint8_t* mask;  // nullptr: no SOLID cells, the force is zero
+  double* partial;
+  double* out;
+  uint32_t nx, ny, nz;
+  uint64_t pstride;
+  int32_t face[6];
   double rho0;
 };
 
@@ -169,6 +193,9 @@ hipError_t launch_init(int lattice, int storage, const InitArgs& a, uint32_t n,
                        hipStream_t st);
 hipError_t launch_moments(int lattice, int storage, const MomentArgs& a,
                           uint32_t n, hipStream_t st);
+hipError_t launch_accum(int lattice, int storage, const AccumArgs& a, uint32_t n,
+                        hipStream_t st);
+hipError_t launch_force(int lattice, int storage, const ForceArgs& a, hipStream_t st);
 hipError_t launch_probe(int lattice, int storage, const ProbeArgs& a,
                         uint32_t n, hipStream_t st);
 hipError_t launch_get_pop(int lattice, int storage, const PopArgs& a,

@@ -153,7 +153,8 @@ static void level_layout(Level& L, int lattice, int storage) {
 
 void plan_layout(lbm_ctx* ctx) {
   const lbm_config& c = ctx->cfg;
-  size_t off = 256;  // status words first
+  // status words first, then the partial sums of lbm_force
+  size_t off = 256 + align_up(sizeof(double) * 3 * kForceBlocks, 256);
   for (int l = 0; l < ctx->nlevels; ++l) {
     Level& L = ctx->lv[l];
     level_layout(L, c.lattice, c.storage);
@@ -261,6 +262,7 @@ namespace hrlbm {
 
 void assign_pointers(lbm_ctx* ctx) {
   ctx->status = (int*)ctx->mem;
+  ctx->reduce = (double*)(ctx->mem + 256);
   for (int l = 0; l < ctx->nlevels; ++l) {
     Level& L = ctx->lv[l];
     char* b = ctx->mem + L.base_off;
@@ -606,6 +608,52 @@ int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n, double* rho_
   a.rho0 = ctx->cfg.rho0;
   hipError_t e = launch_probe(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)n, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "probe launch");
+  return LBM_OK;
+}
+
+int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  if (!sum1 && !sum2) return LBM_OK;
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  const Level& L = ctx->lv[level];
+  AccumArgs a{};
+  a.src = L.buf[L.cur];
+  a.mask = L.has_mask ? L.mask : nullptr;
+  a.sum1 = sum1;
+  a.sum2 = sum2;
+  a.ncell = (uint32_t)L.N;
+  a.pstride = L.pstride;
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_accum(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "accumulate launch");
+  return LBM_OK;
+}
+
+int lbm_force(lbm_ctx* ctx, int level, double* out) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels || !out)
+    return set_error(LBM_EINVAL, "level %d / output", level);
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  const Level& L = ctx->lv[level];
+  ForceArgs a{};
+  a.src = L.buf[L.cur];
+  a.mask = L.has_mask ? L.mask : nullptr;
+  a.partial = ctx->reduce;
+  a.out = out;
+  a.nx = (uint32_t)L.nx;
+  a.ny = (uint32_t)L.ny;
+  a.nz = (uint32_t)L.nz;
+  a.pstride = L.pstride;
+  for (int f = 0; f < 6; ++f) a.face[f] = L.face[f];
+  a.rho0 = ctx->cfg.rho0;
+  hipError_t e = launch_force(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "force launch");
   return LBM_OK;
 }
 

@@ -52,6 +52,7 @@ struct lbm_ctx {
   bool owns_mem = false;
   size_t total_bytes = 0;
   int* status = nullptr;
+  double* reduce = nullptr;  // kForceBlocks x 3 partial sums
   bool status_cleared = false;
   bool unstable = false;
   bool initialised = false;

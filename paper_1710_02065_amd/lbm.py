@@ -30,7 +30,7 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
-           "lbm_moments", "lbm_probe", "lbm_get_populations", "lbm_set_populations",
+           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_get_populations", "lbm_set_populations",
            "lbm_step_batch", "lbm_autotune", "lbm_destroy", "lbm_lattice_table",
            "lbm_last_error"]
 
@@ -84,6 +84,8 @@ def lib():
         L.lbm_level_shape.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.lbm_moments.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_probe.argtypes = [vp, C.c_int, vp, C.c_int, dp]
+        L.lbm_force.argtypes = [vp, C.c_int, dp]
+        L.lbm_accumulate.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_get_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
@@ -163,6 +165,14 @@ def lbm_probe(ctx, level, cells, rho_out):
     return _check(lib().lbm_probe(ctx, level, _ptr(cells), int(cells.numel()), _ptr(rho_out)))
 
 
+def lbm_accumulate(ctx, level, sum1, sum2):
+    return _check(lib().lbm_accumulate(ctx, level, _ptr(sum1), _ptr(sum2)))
+
+
+def lbm_force(ctx, level, out):
+    return _check(lib().lbm_force(ctx, level, _ptr(out)))
+
+
 def lbm_get_populations(ctx, level, out):
     return _check(lib().lbm_get_populations(ctx, level, _ptr(out)))
 
@@ -240,11 +250,14 @@ class Simulation:
         self.device = torch.device("cuda", cfg.device)
         self.ctx = lbm_create(cfg)
         self.q = cfg.lattice
+        # bound now: module globals may already be gone when a late __del__
+        # runs at interpreter exit
+        self._destroy = lib().lbm_destroy
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
-            lbm_destroy(ctx)
+            self._destroy(ctx)
             self.ctx = None
 
     def close(self):
@@ -301,6 +314,19 @@ class Simulation:
         u = t.empty(3, N, dtype=t.float64, device=self.device)
         lbm_moments(self.ctx, level, rho, u)
         return rho, u
+
+    def force(self, level=0, out=None):
+        """Momentum-exchange force on the SOLID cells (3 FP64 on the
+        device); `out` may be a 3-element slice of a longer series."""
+        if out is None:
+            out = self.torch.empty(3, dtype=self.torch.float64, device=self.device)
+        lbm_force(self.ctx, level, out)
+        return out
+
+    def accumulate(self, sum1, sum2=None, level=0):
+        """Add rho - rho0 (and its square) of the current state to the
+        device FP64 arrays sum1 (and sum2) of one entry per cell."""
+        lbm_accumulate(self.ctx, level, sum1, sum2)
 
     def populations(self, level=0):
         t = self.torch

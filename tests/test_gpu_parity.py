@@ -327,3 +327,129 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     c = gpu_sim(case, "f32").init(rho, u, p)  # picks the cached size
     c.step(7)
     np.testing.assert_array_equal(c.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
+def test_poisoned_job_does_not_change_the_others():
+    """A batch where one context goes unstable: it reports LBM_EUNSTABLE,
+    the others report OK and match their solo runs bitwise."""
+    from paper_1710_02065_amd import lbm
+    cases = [dict(name="ok0", q=9, shape=(64, 48, 1), tau=0.6),
+             dict(name="bad", q=9, shape=(40, 40, 1), tau=0.6),
+             dict(name="ok1", q=9, shape=(50, 70, 1), tau=0.7)]
+    fields = [W.random_state(c["shape"], seed=70 + k, d=2) for k, c in enumerate(cases)]
+    rho_bad = fields[1][0].copy()
+    rho_bad[100] = np.nan
+    fields[1] = (rho_bad,) + fields[1][1:]
+    log("poisoned batch")
+    solo = [gpu_sim(c, "f32").init(*f).step(30).populations().cpu().numpy()
+            for c, f in zip(cases, fields)]
+    sims = [gpu_sim(c, "f32").init(*f) for c, f in zip(cases, fields)]
+    lbm.lbm_step_batch([s.ctx for s in sims], [30, 30, 30])
+    for k in (0, 2):
+        np.testing.assert_array_equal(sims[k].populations().cpu().numpy(), solo[k])
+        sims[k].sync()
+    with pytest.raises(lbm.LbmError) as e:
+        sims[1].sync()
+    assert e.value.code == lbm.LBM_EUNSTABLE
+
+
+def _force_cases():
+    box = (20, 18, 16)
+    mask = W.closed_box_mask(*box)
+    mask[W.jet_inlet_mask(*box, D=6) == W.INLET] = W.INLET
+    boxcase = dict(name="box+jet", q=19, shape=box, tau=0.55, ma=0.2, seed=3,
+                   inlet_noise=0.01, mask=mask, face_bc=(2, 2, 1, 1, 2, 2),
+                   sponge_width=(0, 6, 3, 3, 3, 3), chi_max=0.2)
+    return [channel_case(9), channel_case(19), channel_case(27), boxcase]
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_force_parity_f64(k):
+    """Momentum-exchange force on the SOLID cells against the oracle's,
+    normwise within 1e-12, at two time levels; repeated calls bitwise."""
+    case = _force_cases()[k]
+    shape = case["shape"]
+    d = dim(case["q"])
+    rho, u = W.uniform_perturbed(shape, 0.1, (1, 0, 0), seed=9, rel_noise=1e-2, d=d)
+    sim = gpu_sim(case, "f64")
+    log("force %s q=%d" % (case["name"], case["q"]))
+    sim.init(rho, u, None, case["mask"])
+    g = oracle_grid(case).init(rho, u)
+    for steps in (0, 17):
+        sim.step(steps)
+        g.step(steps)
+        F1 = sim.force().cpu().numpy()
+        F2 = sim.force().cpu().numpy()
+        sim.sync()
+        Fo = g.force()
+        assert np.abs(Fo).max() > 1e-3
+        assert normwise(F1, Fo) <= F64_TOL
+        assert np.array_equal(F1, F2)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32s", "f16s"])
+def test_force_low_precision_same_state(storage):
+    """In the narrow formats the force is summed in FP64 from the stored
+    values: the oracle's force of the same (exactly converted) state agrees
+    up to summation order."""
+    case = channel_case(19)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=2, rel_noise=1e-2, d=3)
+    sim = gpu_sim(case, storage)
+    log("force lowprec %s" % storage)
+    sim.init(rho, u, None, case["mask"])
+    sim.step(9)
+    F = sim.force().cpu().numpy()
+    f = sim.populations().cpu().numpy()
+    sim.sync()
+    g = oracle_grid(case)
+    g.set_populations(f)
+    assert normwise(F, g.force()) <= 1e-13
+
+
+def test_force_series_into_slices_and_no_mask_is_zero():
+    case = channel_case(9)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=4, rel_noise=1e-2, d=2)
+    sim = gpu_sim(case, "f32")
+    log("force series")
+    sim.init(rho, u, None, case["mask"])
+    series = torch.zeros(5, 3, dtype=torch.float64, device="cuda")
+    for k in range(5):
+        sim.step(3)
+        sim.force(out=series[k])
+    ref = sim.force().cpu().numpy()
+    sim.sync()
+    assert np.array_equal(series[4].cpu().numpy(), ref)
+    assert np.all(series[:, 0].cpu().numpy() != 0)
+    plain = gpu_sim(dict(q=9, shape=(32, 16, 1)), "f32")
+    plain.init()
+    assert np.all(plain.force().cpu().numpy() == 0.0)
+
+
+def test_accumulate_matches_oracle_moments():
+    """Running sums of rho - rho0 and its square over sampled steps against
+    the same sums of the oracle's densities.  The oracle forms rho - rho0
+    from a full rho of about 1, so each term carries an absolute rounding of
+    about 1e-16 against deviations of about 1e-3: bound 1e-11 normwise."""
+    case = channel_case(9)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=12, rel_noise=2e-2, d=2)
+    sim = gpu_sim(case, "f64")
+    log("accumulate")
+    sim.init(rho, u, None, case["mask"])
+    g = oracle_grid(case).init(rho, u)
+    N = int(np.prod(case["shape"]))
+    s1 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    o1, o2 = np.zeros(N), np.zeros(N)
+    fluid = case["mask"] != W.SOLID
+    for k in range(6):
+        sim.step(4)
+        g.step(4)
+        sim.accumulate(s1, s2)
+        x = np.where(fluid, g.moments()[0] - 1.0, 0.0)
+        o1 += x
+        o2 += x * x
+    sim.sync()
+    assert np.abs(o1).max() > 1e-4
+    assert normwise(s1.cpu().numpy(), o1) <= 1e-11
+    assert normwise(s2.cpu().numpy(), o2) <= 1e-11
+    assert np.all(s1.cpu().numpy()[~fluid] == 0.0)

@@ -164,7 +164,7 @@ def time_steps(sim, torch, steps):
     return a.elapsed_time(b)
 
 
-def other_configs(lbm, torch, steps):
+def other_configs(lbm, torch, steps, shedding_steps):
     """Full-size runs of the other single-GPU configurations (not the
     headline): the D2Q9 cylinder channel and the D3Q27 jet with a 2:1 block."""
     from paper_1710_02065_amd import workloads as W
@@ -188,6 +188,14 @@ def other_configs(lbm, torch, steps):
         note="72 B/LUP populations + 1 B mask; 151 MB of state fits the 256 MB MALL")
     del sim
     torch.cuda.empty_cache()
+    if shedding_steps:
+        # the same channel run long enough for periodic shedding: C_L, St
+        # and C_D by momentum exchange (Sec. III); walls 5 D from the body
+        from paper_1710_02065_amd import cylinder_study
+        w = min(60000, shedding_steps // 2)
+        res["d2q9_cylinder_2048x1024_shedding"] = cylinder_study.run(
+            steps=shedding_steps, window=w, acoustics=False, log=log)
+        torch.cuda.empty_cache()
     # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
     # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]
     shape = (384, 256, 256)
@@ -258,6 +266,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--config-steps", type=int, default=500)
+    ap.add_argument("--shedding-steps", type=int, default=160000,
+                    help="cylinder channel steps for C_L / St (0: skip)")
     ap.add_argument("--precision-horizons", type=lambda s: [int(x) for x in s.split(",")],
                     default=[500, 1000, 2000, 5000])
     ap.add_argument("--serve-jobs", type=int, default=48)
@@ -358,7 +368,7 @@ def main():
     out["config"]["workgroup"] = wg32
     if not args.no_configs:
         log("other configurations")
-        out["configs"] = other_configs(lbm, torch, args.config_steps)
+        out["configs"] = other_configs(lbm, torch, args.config_steps, args.shedding_steps)
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving: %d jobs, step scale %g" % (args.serve_jobs, args.serve_step_scale))

@@ -27,6 +27,12 @@
  *    Each basis element k is rebuilt as w_i H_k,i c_k / N_k, with N_k the
  *    lattice norm sum_i w_i H_k,i^2, so the rebuilt populations carry the
  *    target third-order moment c_k exactly.
+ *  - full recursive regularization (Sec. II.A, order n > 2): on D2Q9 and
+ *    D3Q27 every Hermite polynomial the lattice resolves (degree <= 2 per
+ *    axis: up to fourth order in 2D and sixth in 3D), coefficients
+ *    rho u...u (eq. recursive1) and the eq. (recursive2) recursion.  D3Q19
+ *    is refused: the paper names only D2Q9 and D3Q27 as carrying the
+ *    property that makes this expansion exact.
  *  - sponge (Sec. II.C, eqs. spongeLB, dampingLBM, modifiedMoments): the
  *    unspecified factors n and m are 1/2, which makes the homogeneous decay
  *    rate of the BGK variant equal the effective damping sigma_eff the
@@ -72,6 +78,7 @@ typedef struct {
   int xi[27][3];
   double w[27];
   int opp[27];
+  int full; /* 1: full recursive regularization (D2Q9 and D3Q27 only) */
 } ora_lattice;
 
 /* Fill *L for lattice id 9, 19 or 27; returns 0, or -1 for an unknown id. */
@@ -190,6 +197,77 @@ static double ora_third_order(const ora_lattice* L, int i, double a3[3][3][3]) {
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Full recursive regularization (Sec. II.A, expansion to order n > 2 on the */
+/* lattices with the "special property", D2Q9 and D3Q27).  These are tensor  */
+/* products of the 1D three-velocity quadrature, on which the 1D Hermite     */
+/* polynomial of degree 3 vanishes (xi^3 = xi and 3 cs^2 = 1); the Hermite   */
+/* polynomials they resolve are the products He_nx(xi_x) He_ny(xi_y)        */
+/* He_nz(xi_z) with every n_a <= 2, mutually orthogonal under the weights,   */
+/* with norms prod_a n_a! cs^(2 n_a).  A multi-index (nx, ny, nz) stands for */
+/* the tensor component whose index list holds nx x's, ny y's and nz z's;    */
+/* summing the contraction H^(n):a^(n)/(n! cs^2n) over the index lists that  */
+/* share it gives H_k a_k / N_k.                                             */
+/* ------------------------------------------------------------------------ */
+
+/* 1D Hermite polynomial of degree n <= 2 for the weight of variance cs^2. */
+static double ora_he(int n, double x) {
+  return n == 0 ? 1.0 : (n == 1 ? x : x * x - ORA_CS2);
+}
+
+/* Non-equilibrium coefficient a^n_neq of the index list s[0..n-1] by
+ * eq. (recursive2): a^n = a^(n-1) u_{s_n} plus, for every earlier index s_k,
+ * a2_{s_k s_n} times the product of u over the remaining n - 2 indices;
+ * a^0_neq = a^1_neq = 0 and a^2_neq is a2 itself. */
+static double ora_aneq_rec(const int* s, int n, const double u[3],
+                           double a2[3][3]) {
+  double r;
+  int k, j;
+  if (n < 2) return 0.0;
+  if (n == 2) return a2[s[0]][s[1]];
+  r = ora_aneq_rec(s, n - 1, u, a2) * u[s[n - 1]];
+  for (k = 0; k < n - 1; ++k) {
+    double p = a2[s[k]][s[n - 1]];
+    for (j = 0; j < n - 1; ++j)
+      if (j != k) p *= u[s[j]];
+    r += p;
+  }
+  return r;
+}
+
+/* sum over every resolved multi-index k of order >= min_order:
+ *   w_i H_k(xi_i) A_k / N_k
+ * with A_k = rho u_x^nx u_y^ny u_z^nz (eq. recursive1) when a2 is NULL, and
+ * the eq. (recursive2) coefficient of a2 otherwise. */
+static void ora_full_sum(const ora_lattice* L, double rho, const double u[3],
+                         double a2[3][3], int min_order, double* out) {
+  int n[3], i;
+  const int top = 2;
+  for (i = 0; i < L->q; ++i) out[i] = 0.0;
+  for (n[2] = 0; n[2] <= (L->d == 3 ? top : 0); ++n[2])
+    for (n[1] = 0; n[1] <= top; ++n[1])
+      for (n[0] = 0; n[0] <= top; ++n[0]) {
+        int seq[6], len = 0, a, r;
+        double A, Nk = 1.0;
+        for (a = 0; a < 3; ++a)
+          for (r = 0; r < n[a]; ++r) seq[len++] = a;
+        if (len < min_order) continue;
+        if (a2) {
+          A = ora_aneq_rec(seq, len, u, a2);
+        } else {
+          A = rho;
+          for (r = 0; r < len; ++r) A *= u[seq[r]];
+        }
+        for (a = 0; a < 3; ++a)
+          Nk *= (n[a] == 2 ? 2.0 * ORA_CS2 * ORA_CS2 : (n[a] == 1 ? ORA_CS2 : 1.0));
+        for (i = 0; i < L->q; ++i) {
+          double H = 1.0;
+          for (a = 0; a < 3; ++a) H *= ora_he(n[a], (double)L->xi[i][a]);
+          out[i] += L->w[i] * H * A / Nk;
+        }
+      }
+}
+
 /* Extended equilibrium f^{eqH}_i(rho, u) of eq. (eqH): the second-order
  * polynomial of eq. (truncatedEq) plus the third-order Hermite terms with the
  * equilibrium coefficients a3_eq = rho u u u of eq. (recursive1). */
@@ -198,6 +276,10 @@ static void ora_feq(const ora_lattice* L, double rho, const double u[3],
   const double cs2 = ORA_CS2, cs4 = ORA_CS2 * ORA_CS2;
   double a3[3][3][3];
   int i, a, b, c;
+  if (L->full) { /* every resolved order, coefficients rho u...u */
+    ora_full_sum(L, rho, u, NULL, 0, feq);
+    return;
+  }
   for (a = 0; a < 3; ++a)
     for (b = 0; b < 3; ++b)
       for (c = 0; c < 3; ++c) a3[a][b][c] = rho * u[a] * u[b] * u[c];
@@ -220,6 +302,10 @@ static void ora_fneq(const ora_lattice* L, const double u[3],
   const double cs4 = ORA_CS2 * ORA_CS2;
   double a3[3][3][3];
   int i, a, b, c;
+  if (L->full) { /* orders 2 ... 2d from the recursion */
+    ora_full_sum(L, 0.0, u, a2, 2, fneq);
+    return;
+  }
   for (a = 0; a < 3; ++a)
     for (b = 0; b < 3; ++b)
       for (c = 0; c < 3; ++c)
@@ -242,19 +328,38 @@ static void ora_unpack6(const double* p, double t[3][3]) {
   t[1][2] = t[2][1] = p[5];
 }
 
-void ora_equilibrium(int lattice, double rho, const double* u, double* feq) {
+/* Lattice of a grid: the velocity set plus the regularization order;
+ * returns -1 for an unknown id or full order on D3Q19. */
+static int ora_lattice_order(int id, int full, ora_lattice* L) {
+  if (ora_make_lattice(id, L)) return -1;
+  if (full && id == 19) return -1;
+  L->full = full ? 1 : 0;
+  return 0;
+}
+
+void ora_equilibrium_ex(int lattice, int full, double rho, const double* u,
+                        double* feq) {
   ora_lattice L;
-  if (ora_make_lattice(lattice, &L)) return;
+  if (ora_lattice_order(lattice, full, &L)) return;
   ora_feq(&L, rho, u, feq);
+}
+
+void ora_noneq_ex(int lattice, int full, const double* u,
+                  const double* a2packed, double* fneq) {
+  ora_lattice L;
+  double a2[3][3];
+  if (ora_lattice_order(lattice, full, &L)) return;
+  ora_unpack6(a2packed, a2);
+  ora_fneq(&L, u, a2, fneq);
+}
+
+void ora_equilibrium(int lattice, double rho, const double* u, double* feq) {
+  ora_equilibrium_ex(lattice, 0, rho, u, feq);
 }
 
 void ora_noneq(int lattice, const double* u, const double* a2packed,
                double* fneq) {
-  ora_lattice L;
-  double a2[3][3];
-  if (ora_make_lattice(lattice, &L)) return;
-  ora_unpack6(a2packed, a2);
-  ora_fneq(&L, u, a2, fneq);
+  ora_noneq_ex(lattice, 0, u, a2packed, fneq);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -319,11 +424,17 @@ static void ora_collide_cell(const ora_lattice* L, const double* f, double tau,
   }
 }
 
+void ora_collide_ex(int lattice, int full, const double* f, double tau,
+                    double chi, double rho_ref, const double* u_ref,
+                    double* post) {
+  ora_lattice L;
+  if (ora_lattice_order(lattice, full, &L)) return;
+  ora_collide_cell(&L, f, tau, chi, rho_ref, u_ref, post, NULL, NULL, NULL);
+}
+
 void ora_collide(int lattice, const double* f, double tau, double chi,
                  double rho_ref, const double* u_ref, double* post) {
-  ora_lattice L;
-  if (ora_make_lattice(lattice, &L)) return;
-  ora_collide_cell(&L, f, tau, chi, rho_ref, u_ref, post, NULL, NULL, NULL);
+  ora_collide_ex(lattice, 0, f, tau, chi, rho_ref, u_ref, post);
 }
 
 /* Standard LBM-BGK collision, eq. (standardLB) with the second-order
@@ -395,6 +506,7 @@ typedef struct {
   double chi_max, rho_ref, u_ref[3];
   uint64_t seed;
   double inlet_noise;
+  int full_order;           /* 1: full recursive regularization */
 } ora_grid;
 
 /* Sponge strength chi(x) = chi_max * max over faces of the polynomial
@@ -512,7 +624,7 @@ void ora_init(const ora_grid* g, const double* rho, const double* u,
               const double* pineq, double* f) {
   ora_lattice L;
   int64_t N = g->nx * g->ny * g->nz, c;
-  if (ora_make_lattice(g->lattice, &L)) return;
+  if (ora_lattice_order(g->lattice, g->full_order, &L)) return;
 #pragma omp parallel for schedule(static)
   for (c = 0; c < N; ++c) {
     double r = rho ? rho[c] : g->rho0, uu[3], p6[6] = {0, 0, 0, 0, 0, 0};
@@ -541,7 +653,7 @@ void ora_step_ex(const ora_grid* g, const uint8_t* mask, const uint8_t* skip,
                  double* rho_out, double* u_out, double* a2_out) {
   ora_lattice L;
   int64_t N = g->nx * g->ny * g->nz, row;
-  if (ora_make_lattice(g->lattice, &L)) return;
+  if (ora_lattice_order(g->lattice, g->full_order, &L)) return;
 #pragma omp parallel for schedule(static)
   for (row = 0; row < g->ny * g->nz; ++row) {
     int64_t y = row % g->ny, z = row / g->ny, x;
@@ -736,7 +848,7 @@ void ora_ref_fill_ring(const ora_refined* R, const uint8_t* fring,
   int64_t Nc = c->nx * c->ny * c->nz, Nf = f->nx * f->ny * f->nz, cf;
   const double alpha_cf = f->tau / (2.0 * c->tau);
   int d;
-  if (ora_make_lattice(c->lattice, &L)) return;
+  if (ora_lattice_order(c->lattice, c->full_order, &L)) return;
   d = L.d;
 #pragma omp parallel for schedule(static)
   for (cf = 0; cf < Nf; ++cf) {
@@ -794,7 +906,7 @@ void ora_ref_import(const ora_refined* R, const uint8_t* crole,
   int64_t Nc = c->nx * c->ny * c->nz, Nf = f->nx * f->ny * f->nz, cc;
   const double alpha_fc = 2.0 * c->tau / f->tau;
   const double w1[3] = {0.25, 0.5, 0.25};
-  if (ora_make_lattice(c->lattice, &L)) return;
+  if (ora_lattice_order(c->lattice, c->full_order, &L)) return;
 #pragma omp parallel for schedule(static)
   for (cc = 0; cc < Nc; ++cc) {
     int64_t p[3], kc[3];

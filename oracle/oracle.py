@@ -31,6 +31,10 @@ def lib():
         L.ora_noneq.argtypes = [C.c_int, dp, dp, dp]
         L.ora_collide.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.ora_collide_bgk.argtypes = L.ora_collide.argtypes
+        L.ora_equilibrium_ex.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp]
+        L.ora_noneq_ex.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.ora_collide_ex.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double,
+                                     C.c_double, dp, dp]
         L.ora_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.ora_splitmix64.restype = C.c_uint64
         L.ora_sponge_chi.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64]
@@ -72,7 +76,7 @@ class OraGrid(C.Structure):
         ("u_in", C.c_double * 3),
         ("face_bc", C.c_int * 6), ("sponge_width", C.c_int * 6),
         ("chi_max", C.c_double), ("rho_ref", C.c_double), ("u_ref", C.c_double * 3),
-        ("seed", C.c_uint64), ("inlet_noise", C.c_double),
+        ("seed", C.c_uint64), ("inlet_noise", C.c_double), ("full_order", C.c_int),
     ]
 
 
@@ -89,27 +93,47 @@ def lattice(q):
             np.array(opp[:], dtype=np.int64))
 
 
-def equilibrium(q, rho, u):
+def _check_full(q, full):
+    if full and q not in (9, 27):
+        raise ValueError("full recursive regularization needs D2Q9 or D3Q27")
+
+
+def equilibrium(q, rho, u, full=False):
+    """f^eqH(rho, u); full=True expands to every order the lattice resolves
+    (default: third order)."""
+    _check_full(q, full)
     out = np.zeros(q)
     u3 = _f64(list(u) + [0.0] * (3 - len(u)))
-    lib().ora_equilibrium(q, float(rho), _dp(u3), _dp(out))
+    if full:
+        lib().ora_equilibrium_ex(q, 1, float(rho), _dp(u3), _dp(out))
+    else:
+        lib().ora_equilibrium(q, float(rho), _dp(u3), _dp(out))
     return out
 
 
-def noneq(q, u, a2):
-    """a2 packed (xx, yy, zz, xy, xz, yz)."""
+def noneq(q, u, a2, full=False):
+    """f^neqH(a2, u); a2 packed (xx, yy, zz, xy, xz, yz)."""
+    _check_full(q, full)
     out = np.zeros(q)
     u3 = _f64(list(u) + [0.0] * (3 - len(u)))
     a2 = _f64(a2, 6)
-    lib().ora_noneq(q, _dp(u3), _dp(a2), _dp(out))
+    if full:
+        lib().ora_noneq_ex(q, 1, _dp(u3), _dp(a2), _dp(out))
+    else:
+        lib().ora_noneq(q, _dp(u3), _dp(a2), _dp(out))
     return out
 
 
-def collide(q, f, tau, chi=0.0, rho_ref=1.0, u_ref=(0.0, 0.0, 0.0)):
+def collide(q, f, tau, chi=0.0, rho_ref=1.0, u_ref=(0.0, 0.0, 0.0), full=False):
+    _check_full(q, full)
     f = _f64(f, q)
     out = np.zeros(q)
     ur = _f64(list(u_ref) + [0.0] * (3 - len(u_ref)))
-    lib().ora_collide(q, _dp(f), float(tau), float(chi), float(rho_ref), _dp(ur), _dp(out))
+    if full:
+        lib().ora_collide_ex(q, 1, _dp(f), float(tau), float(chi), float(rho_ref), _dp(ur),
+                             _dp(out))
+    else:
+        lib().ora_collide(q, _dp(f), float(tau), float(chi), float(rho_ref), _dp(ur), _dp(out))
     return out
 
 
@@ -131,13 +155,16 @@ class Grid:
     Parameters mirror the library's configuration: lattice q in {9, 19, 27},
     shape (nx, ny, nz) with nz = 1 in 2D, tau, rho0, inlet velocity u_in,
     per-face rules (x-, x+, y-, y+, z-, z+), sponge widths, chi_max and the
-    sponge reference state, seed and inlet noise for inlet cells.
+    sponge reference state, seed and inlet noise for inlet cells;
+    full_order=True regularizes to every order the lattice resolves (D2Q9
+    and D3Q27) instead of the third.
     """
 
     def __init__(self, q, nx, ny, nz=1, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
                  face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0,
                  rho_ref=1.0, u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0,
-                 mask=None, level=0):
+                 mask=None, level=0, full_order=False):
+        _check_full(q, full_order)
         self.q = q
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -151,6 +178,7 @@ class Grid:
         g.chi_max, g.rho_ref = chi_max, rho_ref
         g.u_ref[:] = list(u_ref) + [0.0] * (3 - len(u_ref))
         g.seed, g.inlet_noise = seed, inlet_noise
+        g.full_order = 1 if full_order else 0
         self.g = g
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
         if self.mask is not None:
@@ -230,7 +258,8 @@ class RefinedGrid:
 
     def __init__(self, q, nx, ny, nz, lo, hi, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
                  face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0, rho_ref=1.0,
-                 u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0, mask=None, fine_mask=None):
+                 u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0, mask=None, fine_mask=None,
+                 full_order=False):
         d = 2 if q == 9 else 3
         lo = list(lo) + [0] * (3 - len(lo))
         hi = list(hi) + [0] * (3 - len(hi))
@@ -238,11 +267,13 @@ class RefinedGrid:
         tau_f = (4.0 * tau - 1.0) / 2.0
         self.coarse = Grid(q, nx, ny, nz, tau=tau, rho0=rho0, u_in=u_in, face_bc=face_bc,
                            sponge_width=sponge_width, chi_max=chi_max, rho_ref=rho_ref,
-                           u_ref=u_ref, seed=seed, inlet_noise=inlet_noise, mask=mask, level=0)
+                           u_ref=u_ref, seed=seed, inlet_noise=inlet_noise, mask=mask, level=0,
+                           full_order=full_order)
         self.fine = Grid(q, *fshape, tau=tau_f, rho0=rho0, u_in=u_in,
                          face_bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW,
                                   OUTFLOW if d == 3 else PERIODIC, OUTFLOW if d == 3 else PERIODIC),
-                         seed=seed, inlet_noise=inlet_noise, mask=fine_mask, level=1)
+                         seed=seed, inlet_noise=inlet_noise, mask=fine_mask, level=1,
+                         full_order=full_order)
         R = OraRefined()
         R.c = self.coarse.g
         R.f = self.fine.g

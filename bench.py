@@ -58,12 +58,13 @@ def measured_traffic(name):
     return int(d["bytes_per_launch"])
 
 
-def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0):
+def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0, lattice=19, flags=0):
     """Initialise, warm up, pick the workgroup size with the library's
     autotuner (unless one is given), then time `steps` steps with HIP events
     on the launch stream."""
     rho, u = fields
-    sim = lbm.Simulation(lattice=19, shape=(n, n, n), tau=0.52, storage=storage, block=block)
+    sim = lbm.Simulation(lattice=lattice, shape=(n, n, n), tau=0.52, storage=storage,
+                         block=block, flags=flags)
     sim.init(rho, u)
     sim.step(warmup)
     sim.sync()
@@ -333,6 +334,22 @@ def main():
                                 speedup_vs_f32=round(mv / mlups32, 3), workgroup=sv.block)
             del sv
             torch.cuda.empty_cache()
+        # regularization order on D3Q27 (the lattice that resolves up to sixth
+        # order): third order against the full recursive expansion
+        order = {}
+        for st in ("f32", "f16s"):
+            for name, fl in (("third", 0), ("full", lbm.LBM_FULL_ORDER)):
+                log("timing d3q27 %s %s" % (st, name))
+                sv, msv = run_gpu(lbm, torch, st, n, max(args.steps // 4, 50), args.warmup // 4,
+                                  fields, args.block, lattice=27, flags=fl)
+                b = 2 * 27 * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
+                ns = max(args.steps // 4, 50)
+                order["d3q27_%s_%s" % (st, name)] = dict(
+                    mlups=round(N * ns / (msv * 1e3), 1), bytes_per_lup=b,
+                    hbm_gbs=round(b * N * ns / (msv / 1e3) / 1e9, 1), workgroup=sv.block)
+                del sv
+                torch.cuda.empty_cache()
+        variants["regularization_order_d3q27_%d" % n] = order
         log("precision study: f64 / f32 / f32s / f16s side by side")
         precision = precision_study(lbm, torch, n, fields, args.precision_horizons)
 

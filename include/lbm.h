@@ -94,6 +94,14 @@ enum {
 #define LBM_ALLOW_HIGH_MA 0x1u /* accept Ma > 0.6 (beyond the stable range
                                   reported in the paper's conclusions) */
 #define LBM_NO_GRAPH 0x2u      /* never replay step sequences as hipGraphs */
+#define LBM_FULL_ORDER 0x4u    /* full recursive regularization (Sec. II.A,
+                                  order n > 2): every Hermite polynomial the
+                                  lattice resolves, up to fourth order on
+                                  D2Q9 and sixth on D3Q27, with coefficients
+                                  from eqs. (recursive1) and (recursive2);
+                                  without it, third order.  D2Q9 and D3Q27
+                                  only (the lattices with the property the
+                                  paper relies on); EINVAL on D3Q19. */
 
 typedef struct lbm_config {
   uint32_t struct_size;  /* sizeof(lbm_config); set by lbm_config_init */
@@ -115,7 +123,7 @@ typedef struct lbm_config {
   uint64_t seed;         /* inlet noise seed */
   double inlet_noise;    /* relative inlet velocity noise amplitude */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
-  uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH */
+  uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER */
   uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
 } lbm_config;
 

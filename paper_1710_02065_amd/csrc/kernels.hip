@@ -781,12 +781,14 @@ hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
     case 9: return launch_sweep_l<Lattice<9>>(h, storage, block, st);
     case 19: return launch_sweep_l<Lattice<19>>(h, storage, block, st);
     case 27: return launch_sweep_l<Lattice<27>>(h, storage, block, st);
+    case kFullOrderCode + 9: return launch_sweep_l<Lattice<9, true>>(h, storage, block, st);
+    case kFullOrderCode + 27: return launch_sweep_l<Lattice<27, true>>(h, storage, block, st);
   }
   return hipErrorInvalidValue;
 }
 
 // dispatch of the companion kernels over lattice and storage
-#define HRLBM_DISPATCH(NAME, ARGS)                                            \
+#define HRLBM_DISPATCH(NAME, ARGS, FULL)                                      \
   template <class L, class S>                                                 \
   static void NAME##_t(const ARGS& a, uint32_t n, hipStream_t st) {           \
     const uint32_t blocks = (n + 255) / 256;                                  \
@@ -807,20 +809,26 @@ hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
       case 9: NAME##_l<Lattice<9>>(storage, a, n, st); break;                 \
       case 19: NAME##_l<Lattice<19>>(storage, a, n, st); break;               \
       case 27: NAME##_l<Lattice<27>>(storage, a, n, st); break;               \
+      FULL(NAME)                                                              \
       default: return hipErrorInvalidValue;                                   \
     }                                                                         \
     return hipGetLastError();                                                 \
   }
+// extra cases of the kernels that rebuild populations (collision order)
+#define HRLBM_FULL_CASES(NAME)                                                   \
+  case kFullOrderCode + 9: NAME##_l<Lattice<9, true>>(storage, a, n, st); break; \
+  case kFullOrderCode + 27: NAME##_l<Lattice<27, true>>(storage, a, n, st); break;
+#define HRLBM_NO_CASES(NAME)
 
-HRLBM_DISPATCH(init, InitArgs)
-HRLBM_DISPATCH(moments, MomentArgs)
-HRLBM_DISPATCH(probe, ProbeArgs)
-HRLBM_DISPATCH(accum, AccumArgs)
-HRLBM_DISPATCH(get_pop, PopArgs)
-HRLBM_DISPATCH(set_pop, PopArgs)
-HRLBM_DISPATCH(record_fields, RecordFieldsArgs)
-HRLBM_DISPATCH(ring, RingArgs)
-HRLBM_DISPATCH(import, ImportArgs)
+HRLBM_DISPATCH(init, InitArgs, HRLBM_FULL_CASES)
+HRLBM_DISPATCH(moments, MomentArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(probe, ProbeArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(accum, AccumArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(get_pop, PopArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(set_pop, PopArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(record_fields, RecordFieldsArgs, HRLBM_NO_CASES)
+HRLBM_DISPATCH(ring, RingArgs, HRLBM_FULL_CASES)
+HRLBM_DISPATCH(import, ImportArgs, HRLBM_FULL_CASES)
 
 void fill_fastdiv(uint32_t d, uint32_t out[3]) {
   const FastDiv f = make_fastdiv(d);
@@ -835,6 +843,12 @@ hipError_t launch_batch(int lattice, const BatchJob* jobs, BatchHeader* hdr, int
     case 9: hipLaunchKernelGGL(k_batch<Lattice<9>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
     case 19: hipLaunchKernelGGL(k_batch<Lattice<19>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
     case 27: hipLaunchKernelGGL(k_batch<Lattice<27>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
+    case kFullOrderCode + 9:
+      hipLaunchKernelGGL((k_batch<Lattice<9, true>>), dim3(grid), dim3(block), 0, st, jobs, hdr);
+      break;
+    case kFullOrderCode + 27:
+      hipLaunchKernelGGL((k_batch<Lattice<27, true>>), dim3(grid), dim3(block), 0, st, jobs, hdr);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -855,6 +869,12 @@ int batch_grid(int lattice, int block) {
     case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<9>>, block, 0); break;
     case 19: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<19>>, block, 0); break;
     case 27: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<27>>, block, 0); break;
+    case kFullOrderCode + 9:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<9, true>>, block, 0);
+      break;
+    case kFullOrderCode + 27:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<27, true>>, block, 0);
+      break;
   }
   if (e != hipSuccess || per < 1) per = 1;
   return cus * per;

@@ -206,6 +206,7 @@ struct Coeffs {
   R m1[3];
   R m2[6];  // xx, yy, zz, xy, xz, yz
   R m3[7];  // xxy, xyy, xxz, xzz, yyz, yzz, xyz
+  R mh[L::KH > 0 ? L::KH : 1];  // order >= 4 (full order only), divided by N_k
 };
 
 // Compile-time loop (the index is a constant in the body).
@@ -231,7 +232,16 @@ __device__ __forceinline__ void rebuild_all(const Coeffs<L, R>& c, const R bk[L:
   const R m1s[3] = {(R)3 * c.m1[0], (R)3 * c.m1[1], (R)3 * c.m1[2]};
   const R d2[3] = {(R)4.5 * c.m2[0], (R)4.5 * c.m2[1], (R)4.5 * c.m2[2]};
   const R o2[3] = {(R)9 * c.m2[3], (R)9 * c.m2[4], (R)9 * c.m2[5]};
-  out[0] = (R)L::w(0) * e0;
+  if constexpr (L::KH > 0) {
+    R h0 = e0;
+    static_for<0, L::KH>([&](auto KK) {
+      constexpr double hk = high_h<L>(0, decltype(KK)::value);
+      if constexpr (hk != 0.0) h0 += (R)hk * c.mh[decltype(KK)::value];
+    });
+    out[0] = (R)L::w(0) * h0;
+  } else {
+    out[0] = (R)L::w(0) * e0;
+  }
   static_for<0, (L::Q - 1) / 2>([&](auto K) {
     constexpr int i = 1 + 2 * decltype(K)::value;
     constexpr Dir v = L::dir(i);
@@ -255,6 +265,17 @@ __device__ __forceinline__ void rebuild_all(const Coeffs<L, R>& c, const R bk[L:
     static_for<0, L::K>([&](auto KK) {
       constexpr double hk = basis_h<L>(i, decltype(KK)::value);
       if constexpr (hk != 0.0) odd += (R)hk * bk[decltype(KK)::value];
+    });
+    // orders 4 to 6: even orders join the even part, odd orders the odd
+    static_for<0, L::KH>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      constexpr double hk = high_h<L>(i, k);
+      if constexpr (hk != 0.0) {
+        if constexpr (high_order(L::high(k)) % 2 == 0)
+          even += (R)hk * c.mh[k];
+        else
+          odd += (R)hk * c.mh[k];
+      }
     });
     constexpr R w = (R)L::w(i);
     out[i] = w * (even + odd);
@@ -287,6 +308,65 @@ __device__ __forceinline__ void recursion3(const R u[3], const R A[6], R t[7]) {
   t[kYYZ] = (R)2 * u[1] * yz + u[2] * yy;
   t[kYZZ] = (R)2 * u[2] * yz + u[1] * zz;
   t[kXYZ] = u[0] * yz + u[1] * xz + u[2] * xy;
+}
+
+// u_a^n for n <= 2 (n is a constant after inlining)
+template <class R>
+__device__ __forceinline__ R upow(const R u[3], const R u2[3], int a, int n) {
+  return n == 0 ? (R)1 : (n == 1 ? u[a] : u2[a]);
+}
+
+// packed index of a2_ab in (xx, yy, zz, xy, xz, yz)
+constexpr int pack2(int a, int b) {
+  return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
+}
+
+// Equilibrium and non-equilibrium Hermite coefficients of the high-order
+// polynomial with multi-index m: eq = u^m (times rho by the caller), and the
+// closed form of the recursion eq. (recursive2): a sum over every pair of
+// positions in the index list of a2 on that pair times u over the rest,
+// i.e. sum over a <= b of (n_a n_b, or n_a (n_a - 1) / 2 when a = b)
+// a2_ab u^(m - e_a - e_b).
+template <class R>
+__device__ __forceinline__ void high_terms(const MultiIndex m, const R u[3], const R u2[3],
+                                           const R a2[6], R& eq, R& neq) {
+  eq = upow(u, u2, 0, m.n[0]) * upow(u, u2, 1, m.n[1]) * upow(u, u2, 2, m.n[2]);
+  neq = (R)0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      const int cnt = a == b ? m.n[a] * (m.n[a] - 1) / 2 : m.n[a] * m.n[b];
+      if (cnt == 0) continue;
+      int r[3] = {m.n[0], m.n[1], m.n[2]};
+      r[a] -= 1;
+      r[b] -= 1;
+      neq += (R)cnt * a2[pack2(a, b)] * upow(u, u2, 0, r[0]) * upow(u, u2, 1, r[1]) *
+             upow(u, u2, 2, r[2]);
+    }
+}
+
+// High-order coefficients mh_k = (e rho u^m + chi rho_ref uref^m
+// + omega1 a_neq) / N_k of the full-order rebuild.
+template <class L, class R, bool kSponge>
+__device__ __forceinline__ void high_coeffs(R rho, const R u[3], const R a2[6], R omega1,
+                                            R chi, R rho_ref, const R uref[3],
+                                            Coeffs<L, R>& c) {
+  const R u2[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
+  const R e = kSponge ? (R)1 - chi : (R)1;
+  static_for<0, L::KH>([&](auto KK) {
+    constexpr int k = decltype(KK)::value;
+    constexpr MultiIndex m = L::high(k);
+    R eq, neq;
+    high_terms<R>(m, u, u2, a2, eq, neq);
+    R v = e * rho * eq + omega1 * neq;
+    if constexpr (kSponge) {
+      const R r2[3] = {uref[0] * uref[0], uref[1] * uref[1], uref[2] * uref[2]};
+      v += chi * rho_ref * upow(uref, r2, 0, m.n[0]) * upow(uref, r2, 1, m.n[1]) *
+           upow(uref, r2, 2, m.n[2]);
+    }
+    c.mh[k] = v * (R)(1.0 / high_norm<L>(k));
+  });
 }
 
 // rho u_a u_b u_c for the seven packed components
@@ -463,6 +543,8 @@ __device__ __forceinline__ R collide_moments(R drho, R j[3], const R P[6], R ome
 #pragma unroll
     for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
   }
+  if constexpr (L::KH > 0)
+    high_coeffs<L, R, kSponge>(rho, u, a2, omega1, chi, rho_ref, uref, c);
   R bk[L::K];
   basis_coeffs<L, R>(c.m3, bk);
   rebuild_all<L, R>(c, bk, base, out);
@@ -504,6 +586,8 @@ __device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
   cube3<R>(rho, u, a3e);
 #pragma unroll
   for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
+  if constexpr (L::KH > 0)
+    high_coeffs<L, R, false>(rho, u, a2, omega1, (R)0, (R)0, u, c);
   R bk[L::K];
   basis_coeffs<L, R>(c.m3, bk);
   rebuild_all<L, R>(c, bk, (R)0, out);

@@ -56,11 +56,12 @@ struct Basis3 {
   int sgn[2];
 };
 
+// velocity set, weights and third-order basis of each lattice
 template <int Q>
-struct Lattice;
+struct LatticeSet;
 
 template <>
-struct Lattice<9> {
+struct LatticeSet<9> {
   static constexpr int Q = 9, D = 2, K = 2;
   static constexpr Dir dir(int i) { return kDirs2[i]; }
   static constexpr double w(int i) {
@@ -72,7 +73,7 @@ struct Lattice<9> {
 };
 
 template <>
-struct Lattice<19> {
+struct LatticeSet<19> {
   static constexpr int Q = 19, D = 3, K = 6;
   static constexpr Dir dir(int i) { return kDirs3[i]; }
   static constexpr double w(int i) {
@@ -90,7 +91,7 @@ struct Lattice<19> {
 };
 
 template <>
-struct Lattice<27> {
+struct LatticeSet<27> {
   static constexpr int Q = 27, D = 3, K = 7;
   static constexpr Dir dir(int i) { return kDirs3[i]; }
   static constexpr double w(int i) {
@@ -99,6 +100,53 @@ struct Lattice<27> {
   }
   static constexpr Basis3 basis(int k) { return Basis3{1, {k, 0}, {1, 0}}; }
 };
+
+// ------------------------------------------------------------------------
+// Full recursive regularization (Sec. II.A, order n > 2).  D2Q9 and D3Q27
+// are tensor products of the 1D three-velocity quadrature, on which the 1D
+// Hermite polynomial of degree 3 vanishes (xi^3 = xi, 3 cs^2 = 1).  The
+// polynomials they resolve are He_nx(xi_x) He_ny(xi_y) He_nz(xi_z) with every
+// n_a <= 2.  Those of order 4 and above, in addition to the second- and
+// third-order terms, are listed here by multi-index.
+// ------------------------------------------------------------------------
+struct MultiIndex {
+  int n[3];
+};
+constexpr MultiIndex kHigh2[1] = {{{2, 2, 0}}};
+constexpr MultiIndex kHigh3[10] = {
+    {{2, 2, 0}}, {{2, 0, 2}}, {{0, 2, 2}}, {{2, 1, 1}}, {{1, 2, 1}},  // order 4
+    {{1, 1, 2}}, {{2, 2, 1}}, {{2, 1, 2}}, {{1, 2, 2}},               // 4, 5
+    {{2, 2, 2}}};                                                     // 6
+
+// Lattice seen by the kernels: the velocity set plus the regularization
+// order (kFull: every resolved order; otherwise the third).
+template <int Q, bool F = false>
+struct Lattice : LatticeSet<Q> {
+  static_assert(!F || Q != 19, "full-order regularization needs D2Q9 or D3Q27");
+  static constexpr bool kFull = F;
+  static constexpr int KH = !F ? 0 : (Q == 9 ? 1 : 10);
+  static constexpr MultiIndex high(int k) { return Q == 9 ? kHigh2[k] : kHigh3[k]; }
+};
+
+// 1D Hermite polynomial of degree n <= 2 at an integer velocity component
+constexpr double he1(int n, int v) {
+  return n == 0 ? 1.0 : (n == 1 ? (double)v : (double)(v * v) - kCs2);
+}
+
+// value of high-order polynomial k at direction i, and its lattice norm
+template <class L>
+constexpr double high_h(int i, int k) {
+  const MultiIndex m = L::high(k);
+  const Dir v = L::dir(i);
+  return he1(m.n[0], v.x) * he1(m.n[1], v.y) * he1(m.n[2], v.z);
+}
+template <class L>
+constexpr double high_norm(int k) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::w(i) * high_h<L>(i, k) * high_h<L>(i, k);
+  return s;
+}
+constexpr int high_order(const MultiIndex& m) { return m.n[0] + m.n[1] + m.n[2]; }
 
 // value of basis element k at direction i
 template <class L>

@@ -7,6 +7,10 @@
 
 namespace hrlbm {
 
+// Added to the lattice id (9, 27) to select the full-order regularization
+// in the collision kernels' dispatch.
+constexpr int kFullOrderCode = 1000;
+
 // One sweep of one grid: src -> dst.
 struct SweepHost {
   const void* src;

@@ -249,7 +249,7 @@ static int fill_ring(lbm_ctx* ctx, const void* Ma, double wa, const void* Mb, do
   a.rho0 = ctx->cfg.rho0;
   a.dst = F.buf[F.cur];
   a.pstride = F.pstride;
-  hipError_t e = launch_ring(ctx->cfg.lattice, ctx->cfg.storage, a, a.n, st);
+  hipError_t e = launch_ring(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, a.n, st);
   if (e != hipSuccess) return hip_error(e, "ring launch");
   return LBM_OK;
 }
@@ -276,7 +276,7 @@ int refined_coarse_step(lbm_ctx* ctx, hipStream_t st) {
     h.box_hi[k] = R->hi[k];
   }
   h.rec_n = R->rec_n;
-  hipError_t e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, ctx->block, st);
+  hipError_t e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
   if (e != hipSuccess) return hip_error(e, "coarse sweep launch");
   C.cur ^= 1;
   C.t += 1;
@@ -306,7 +306,7 @@ int refined_coarse_step(lbm_ctx* ctx, hipStream_t st) {
   ia.rho0 = ctx->cfg.rho0;
   ia.dst = C.buf[C.cur];
   ia.pstride = C.pstride;
-  e = launch_import(ctx->cfg.lattice, ctx->cfg.storage, ia, ia.n, st);
+  e = launch_import(kernel_lattice(ctx->cfg), ctx->cfg.storage, ia, ia.n, st);
   if (e != hipSuccess) return hip_error(e, "import launch");
   R->prev = next;
   ctx->t += 1;

@@ -109,6 +109,8 @@ int validate(const lbm_config* cfg) {
   if (!(c.tau > 0.5) || !std::isfinite(c.tau))
     return set_error(LBM_EINVAL, "tau = %g: nu = cs^2 (tau - 1/2) must be > 0", c.tau);
   if (!(c.rho0 > 0)) return set_error(LBM_EINVAL, "rho0 must be > 0");
+  if ((c.flags & LBM_FULL_ORDER) && c.lattice == LBM_D3Q19)
+    return set_error(LBM_EINVAL, "LBM_FULL_ORDER needs D2Q9 or D3Q27 (D3Q19 resolves third order only)");
   if (!(c.ma >= 0) || (c.ma > 0.6 && !(c.flags & LBM_ALLOW_HIGH_MA)))
     return set_error(LBM_EINVAL, "Ma = %g outside [0, 0.6] (set LBM_ALLOW_HIGH_MA)", c.ma);
   if (!(c.chi_max >= 0))
@@ -343,7 +345,7 @@ int check_ready(const lbm_ctx* ctx) {
 int sweep_level(lbm_ctx* ctx, int l, hipStream_t st) {
   Level& L = ctx->lv[l];
   SweepHost h = sweep_args(ctx, l, L.cur, (uint64_t)(L.t + 1));
-  hipError_t e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, ctx->block, st);
+  hipError_t e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
   if (e != hipSuccess) return hip_error(e, "sweep launch");
   L.cur ^= 1;
   L.t += 1;
@@ -398,7 +400,7 @@ static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
     int buf = L.cur;
     for (int64_t s = 0; s < kGraphSteps; ++s) {
       SweepHost h = sweep_args(ctx, 0, buf, (uint64_t)(L.t + 1 + s));
-      e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
+      e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
       if (e != hipSuccess) break;
       buf ^= 1;
     }
@@ -468,7 +470,7 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   a.rho0 = ctx->cfg.rho0;
   a.omega1 = 1.0 - 1.0 / L.tau;
   for (int k = 0; k < 3; ++k) a.uin[k] = ctx->uin[k];
-  e = launch_init(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  e = launch_init(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "init launch");
   // any level that is not a fully periodic, sponge-free, unrefined grid
   // keeps a mask (all FLUID if none was given) with the flag bits

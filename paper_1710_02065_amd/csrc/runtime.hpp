@@ -67,6 +67,12 @@ struct lbm_ctx {
 
 namespace hrlbm {
 
+// Lattice code the collision kernels are dispatched on: the lattice id,
+// plus kFullOrderCode with LBM_FULL_ORDER.
+inline int kernel_lattice(const lbm_config& c) {
+  return c.lattice + ((c.flags & LBM_FULL_ORDER) ? kFullOrderCode : 0);
+}
+
 int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int lattice_dim(int lattice);

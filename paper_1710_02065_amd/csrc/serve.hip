@@ -121,7 +121,7 @@ static int graph_for(BatchRunner* r, int lattice, int block, int grid, GraphEntr
 // One batch of contexts sharing a lattice.
 static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64_t>>& grp) {
   lbm_ctx* c0 = grp[0].first;
-  const int lattice = c0->cfg.lattice;
+  const int lattice = kernel_lattice(c0->cfg);
   const int block = c0->block;
   int rc = ensure_capacity(r, grp.size());
   if (rc != LBM_OK) return rc;
@@ -257,7 +257,7 @@ std::string tune_key(const lbm_ctx* ctx) {
   for (int64_t n = L.N; n > 1; n >>= 2) ++cls;  // log4 of the cell count
   const SweepHost h = sweep_args(ctx, 0, 0, 0);
   char buf[128];
-  std::snprintf(buf, sizeof buf, "%s/q%d/s%d/%s/n4^%d", arch.c_str(), ctx->cfg.lattice,
+  std::snprintf(buf, sizeof buf, "%s/q%d/s%d/%s/n4^%d", arch.c_str(), kernel_lattice(ctx->cfg),
                 ctx->cfg.storage, h.general ? "general" : "periodic", cls);
   return buf;
 }
@@ -300,7 +300,8 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
   // one persistent launch sequence per (lattice, workgroup size)
   std::map<std::pair<int, int>, std::vector<std::pair<lbm_ctx*, int64_t>>> groups;
   for (int k = 0; k < n; ++k)
-    groups[std::make_pair(ctxs[k]->cfg.lattice, ctxs[k]->block)].push_back({ctxs[k], steps[k]});
+    groups[std::make_pair(kernel_lattice(ctxs[k]->cfg), ctxs[k]->block)].push_back(
+        {ctxs[k], steps[k]});
   for (auto& kv : groups) {
     rc = run_group(r, kv.second);
     if (rc != LBM_OK) return rc;
@@ -328,13 +329,13 @@ int lbm_autotune(lbm_ctx* ctx, int trials) {
   float best_ms = 1e30f;
   int best = ctx->block;
   for (int blk : cands) {
-    e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, blk, ctx->stream);
+    e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
     if (e != hipSuccess) break;
     float tot = 0.f;
     for (int t = 0; t < trials && e == hipSuccess; ++t) {
       e = hipEventRecord(a, ctx->stream);
       for (int k = 0; k < reps && e == hipSuccess; ++k)
-        e = launch_sweep(ctx->cfg.lattice, ctx->cfg.storage, h, blk, ctx->stream);
+        e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;

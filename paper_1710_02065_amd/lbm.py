@@ -21,7 +21,7 @@ LBM_PERIODIC, LBM_FREESLIP, LBM_OUTFLOW = 0, 1, 2
 LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH = 0x1, 0x2
+LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER = 0x1, 0x2, 0x4
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}

@@ -38,7 +38,8 @@ def oracle_grid(case):
                   sponge_width=case.get("sponge_width", (0,) * 6),
                   chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
                   u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
-                  inlet_noise=case.get("inlet_noise", 0.0), mask=case.get("mask"))
+                  inlet_noise=case.get("inlet_noise", 0.0), mask=case.get("mask"),
+                  full_order=case.get("full", False))
 
 
 def gpu_sim(case, storage="f64", **kw):
@@ -49,7 +50,8 @@ def gpu_sim(case, storage="f64", **kw):
                 sponge_width=case.get("sponge_width", (0,) * 6),
                 chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
                 u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
-                inlet_noise=case.get("inlet_noise", 0.0))
+                inlet_noise=case.get("inlet_noise", 0.0),
+                flags=lbm.LBM_FULL_ORDER if case.get("full") else 0)
     args.update(kw)
     return lbm.Simulation(**args)
 
@@ -85,7 +87,7 @@ def refined_pair(case):
                        chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
                        u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
                        inlet_noise=case.get("inlet_noise", 0.0), mask=case.get("mask"),
-                       fine_mask=case.get("fine_mask"))
+                       fine_mask=case.get("fine_mask"), full_order=case.get("full", False))
     return og
 
 

@@ -111,3 +111,10 @@ def test_refined_required_bytes_counts_fine_level():
                    refine_hi=(30, 30, 30))
     fine = 41 ** 3 * 19 * 4 * 2
     assert ref >= base + fine
+
+
+def test_full_order_needs_d2q9_or_d3q27():
+    assert required(lattice=19, shape=(16, 16, 16), flags=lbm.LBM_FULL_ORDER) == 0
+    assert "full_order" in lbm.lbm_last_error().lower()
+    assert required(lattice=27, shape=(16, 16, 16), flags=lbm.LBM_FULL_ORDER) > 0
+    assert required(lattice=9, shape=(16, 16, 1), flags=lbm.LBM_FULL_ORDER) > 0

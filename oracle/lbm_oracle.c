@@ -507,6 +507,7 @@ typedef struct {
   uint64_t seed;
   double inlet_noise;
   int full_order;           /* 1: full recursive regularization */
+  int levels;               /* levels of the hierarchy this grid belongs to */
 } ora_grid;
 
 /* Sponge strength chi(x) = chi_max * max over faces of the polynomial
@@ -607,9 +608,12 @@ static double ora_pull(const ora_grid* g, const ora_lattice* L,
 static void ora_inlet_velocity(const ora_grid* g, int64_t cell, int64_t t,
                                double* u) {
   int64_t N = g->nx * g->ny * g->nz;
+  /* one counter block per (time, level): time index times the level count
+   * (at least 2) plus the level */
+  uint64_t nl = g->levels > 2 ? (uint64_t)g->levels : 2u;
   int a;
   for (a = 0; a < 3; ++a) {
-    uint64_t k = (((uint64_t)t * 2u + (uint64_t)g->level) * (uint64_t)N +
+    uint64_t k = (((uint64_t)t * nl + (uint64_t)g->level) * (uint64_t)N +
                   (uint64_t)cell) * 3u + (uint64_t)a;
     double r = ora_uniform_pm1(ora_splitmix64(g->seed, k));
     u[a] = g->u_in[a] * (1.0 + g->inlet_noise * r);

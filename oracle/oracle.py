@@ -77,6 +77,7 @@ class OraGrid(C.Structure):
         ("face_bc", C.c_int * 6), ("sponge_width", C.c_int * 6),
         ("chi_max", C.c_double), ("rho_ref", C.c_double), ("u_ref", C.c_double * 3),
         ("seed", C.c_uint64), ("inlet_noise", C.c_double), ("full_order", C.c_int),
+        ("levels", C.c_int),
     ]
 
 
@@ -163,7 +164,7 @@ class Grid:
     def __init__(self, q, nx, ny, nz=1, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
                  face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0,
                  rho_ref=1.0, u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0,
-                 mask=None, level=0, full_order=False):
+                 mask=None, level=0, full_order=False, levels=1):
         _check_full(q, full_order)
         self.q = q
         self.shape = (nx, ny, nz)
@@ -179,6 +180,7 @@ class Grid:
         g.u_ref[:] = list(u_ref) + [0.0] * (3 - len(u_ref))
         g.seed, g.inlet_noise = seed, inlet_noise
         g.full_order = 1 if full_order else 0
+        g.levels = levels
         self.g = g
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
         if self.mask is not None:
@@ -341,5 +343,129 @@ class RefinedGrid:
             lib().ora_ref_import(C.byref(self.R), _u8p(self.crole), _dp(self.mf[0]),
                                  _dp(self.mf[1]), _dp(self.mf[2]), _dp(self.coarse.f))
             self.M_prev = [a.copy() for a in self.M_next]
+            self.t += 1
+        return self
+
+
+class MultiLevelGrid:
+    """Nested 2:1 refinement with any number of levels: the two-level
+    coupling of Sec. II.B applied at every interface of a chain of boxes
+    (the paper's cylinder and jet setups use four and five levels).
+
+    Level l+1 covers the closed node box boxes[l] = (lo, hi) of level l with
+    half its spacing and half its time step; tau_(l+1) = (4 tau_l - 1) / 2.
+    Each level's outer shell is RING (from its parent), and the shell of
+    [lo+1, hi-1] of its child's box IMPORT (from the child), deeper nodes
+    COVERED.  One step of level l, recursively (eq. convective at each
+    interface):
+      1. sweep level l, recording its pre-collision moments M_l(t+1);
+      2. if l has a child: step the child; RING(child) <- interpolation of
+         (M_l(t) + M_l(t+1)) / 2; step the child; RING(child) <-
+         interpolation of M_l(t+1); IMPORT(l) <- filtered child moments.
+    With one box this is exactly RefinedGrid's schedule.
+    """
+
+    def __init__(self, q, nx, ny, nz, boxes, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
+                 face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0, rho_ref=1.0,
+                 u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0, masks=None,
+                 full_order=False):
+        d = 2 if q == 9 else 3
+        nl = len(boxes) + 1
+        masks = list(masks) if masks is not None else [None] * nl
+        masks += [None] * (nl - len(masks))
+        self.q, self.d, self.nlevels = q, d, nl
+        self.grids = [Grid(q, nx, ny, nz, tau=tau, rho0=rho0, u_in=u_in, face_bc=face_bc,
+                           sponge_width=sponge_width, chi_max=chi_max, rho_ref=rho_ref,
+                           u_ref=u_ref, seed=seed, inlet_noise=inlet_noise, mask=masks[0],
+                           level=0, full_order=full_order, levels=nl)]
+        self.pairs = []
+        t = tau
+        for l, (lo, hi) in enumerate(boxes):
+            lo = list(lo) + [0] * (3 - len(lo))
+            hi = list(hi) + [0] * (3 - len(hi))
+            shape = [2 * (hi[a] - lo[a]) + 1 if a < d else 1 for a in range(3)]
+            t = (4.0 * t - 1.0) / 2.0
+            zf = OUTFLOW if d == 3 else PERIODIC
+            g = Grid(q, *shape, tau=t, rho0=rho0, u_in=u_in,
+                     face_bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW, zf, zf), seed=seed,
+                     inlet_noise=inlet_noise, mask=masks[l + 1], level=l + 1,
+                     full_order=full_order, levels=nl)
+            self.grids.append(g)
+            R = OraRefined()
+            R.c = self.grids[l].g
+            R.f = g.g
+            R.lo[:] = lo
+            R.hi[:] = hi
+            self.pairs.append(R)
+        # roles: crole[l] from level l's child box, ring[l] on level l's shell
+        self.crole = [np.zeros(g.N, dtype=np.uint8) for g in self.grids]
+        self.ring = [np.zeros(g.N, dtype=np.uint8) for g in self.grids]
+        for l, R in enumerate(self.pairs):
+            lib().ora_ref_roles(C.byref(R), _u8p(self.crole[l]), _u8p(self.ring[l + 1]))
+        self.skip = [((self.crole[l] != NORMAL) | (self.ring[l] != 0)).astype(np.uint8)
+                     for l in range(nl)]
+        self.mom = [[np.zeros(g.N), np.zeros((3, g.N)), np.zeros((6, g.N))] for g in self.grids]
+        self.M_prev = [None] * nl
+        self.inited = [False] * nl
+        self.t = 0
+
+    def init(self, level, rho=None, u=None, pineq=None):
+        g = self.grids[level]
+        g.init(rho, u, pineq)
+        N = g.N
+        M = [np.zeros(N), np.zeros((3, N)), np.zeros((6, N))]
+        M[0][:] = g.g.rho0 if rho is None else np.asarray(rho, dtype=float).reshape(N)
+        if u is None:
+            M[1][:] = np.array(g.g.u_in[:])[:, None]
+        else:
+            uu = np.asarray(u, dtype=float).reshape(-1, N)
+            M[1][: uu.shape[0]] = uu
+        if pineq is not None:
+            M[2][:] = np.asarray(pineq, dtype=float).reshape(6, N)
+        if self.d == 2:
+            M[1][2] = 0.0
+            M[2][[2, 4, 5]] = 0.0
+        self.M_prev[level] = M
+        self.inited[level] = True
+        if all(self.inited):
+            for l in range(1, self.nlevels):
+                self._fill_ring(l - 1, self.M_prev[l - 1], 1.0, self.M_prev[l - 1], 0.0)
+            self.t = 0
+            for gg in self.grids:
+                gg.t = 0
+        return self
+
+    def _fill_ring(self, l, Ma, wa, Mb, wb):
+        """RING of level l+1 from level-l moments wa Ma + wb Mb."""
+        lib().ora_ref_fill_ring(C.byref(self.pairs[l]), _u8p(self.ring[l + 1]), _dp(Ma[0]),
+                                _dp(Ma[1]), _dp(Ma[2]), wa, _dp(Mb[0]), _dp(Mb[1]),
+                                _dp(Mb[2]), wb, _dp(self.grids[l + 1].f))
+
+    def _advance(self, l):
+        g = self.grids[l]
+        out = np.empty_like(g.f)
+        r, u, a2 = self.mom[l]
+        lib().ora_step_ex(C.byref(g.g), g._mask_ptr, _u8p(self.skip[l]), _dp(g.f), _dp(out),
+                          g.t + 1, _dp(r), _dp(u), _dp(a2))
+        g.f = out
+        g.t += 1
+        if l + 1 < self.nlevels:
+            # cells the sweep skipped keep their M(t) values in M(t+1)
+            nxt = [a.copy() for a in self.M_prev[l]]
+            upd = self.skip[l] == 0
+            for a, m in zip(nxt, self.mom[l]):
+                a[..., upd] = m[..., upd]
+            self._advance(l + 1)
+            self._fill_ring(l, self.M_prev[l], 0.5, nxt, 0.5)
+            self._advance(l + 1)
+            self._fill_ring(l, nxt, 1.0, nxt, 0.0)
+            mf = self.mom[l + 1]
+            lib().ora_ref_import(C.byref(self.pairs[l]), _u8p(self.crole[l]), _dp(mf[0]),
+                                 _dp(mf[1]), _dp(mf[2]), _dp(g.f))
+            self.M_prev[l] = nxt
+
+    def step(self, n=1):
+        for _ in range(n):
+            self._advance(0)
             self.t += 1
         return self

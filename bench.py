@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -170,6 +172,30 @@ def other_configs(lbm, torch, steps, shedding_steps):
     headline): the D2Q9 cylinder channel and the D3Q27 jet with a 2:1 block."""
     from paper_1710_02065_amd import workloads as W
     res = {}
+    # D2Q9 128^2 periodic Taylor-Green in FP64 (U = 0.05, tau 0.6, 1000
+    # steps): fitted viscosity against cs^2 (tau - 1/2) = 1/30, mass and
+    # momentum drift; a latency-bound size, timed for completeness
+    n1, U1, tau1, T1 = 128, 0.05, 0.6, 1000
+    rho1, u1, S1 = W.taylor_green_2d(n1, U1)
+    sim = lbm.Simulation(lattice=9, shape=(n1, n1, 1), tau=tau1, storage="f64")
+    sim.init(rho1, u1, -2.0 * rho1 * tau1 / 3.0 * S1)
+    mode = torch.from_numpy(W.taylor_green_mode_2d(n1)).cuda()
+    t0 = sim.totals().cpu().numpy()
+    sim.step(100)
+    a0 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
+    ms1 = time_steps(sim, torch, T1 - 100)
+    a1 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
+    t1 = sim.totals().cpu().numpy()
+    sim.sync()
+    k1 = 2 * math.pi / n1
+    nu_fit = -math.log(a1 / a0) / (2 * k1 * k1 * (T1 - 100))
+    res["d2q9_taylor_green_128_f64"] = dict(
+        nu_fit=nu_fit, nu_theory=1.0 / 30.0, nu_rel_error=nu_fit * 30.0 - 1.0,
+        mass_drift=float(abs(t1[0] - t0[0]) / (n1 * n1)),
+        momentum_drift=float(np.abs(t1[1:] - t0[1:]).max() / (n1 * n1)),
+        mlups=round(n1 * n1 * (T1 - 100) / (ms1 * 1e3), 1), steps=T1,
+        note="drifts per cell; 16k cells cannot fill the GPU")
+    del sim
     # D2Q9 2048 x 1024 channel, cylinder D = 100 at (400, 512), Ma 0.2, Re 150
     nx, ny, D = 2048, 1024, 100
     U = 0.2 * math.sqrt(1.0 / 3.0)
@@ -188,6 +214,28 @@ def other_configs(lbm, torch, steps, shedding_steps):
         hbm_gbs=round(bytes_lup * N * steps / (ms / 1e3) / 1e9, 1),
         note="72 B/LUP populations + 1 B mask; 151 MB of state fits the 256 MB MALL")
     del sim
+    torch.cuda.empty_cache()
+    # the channel in FP32 against the FP64 build (equal to the oracle within
+    # 1e-12 in the parity tests) after 2000 steps
+    fields = {}
+    for st in ("f64", "f32"):
+        sv = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150,
+                            storage=st, ma=0.2, face_bc=(2, 2, 1, 1, 0, 0),
+                            sponge_width=(0, 128, 0, 0, 0, 0), chi_max=0.2, rho_ref=1.0,
+                            u_ref=(U, 0, 0), seed=2)
+        sv.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
+        sv.step(2000)
+        fields[st] = sv.moments()
+        sv.sync()
+        del sv
+    (r64, u64), (r32, u32) = fields["f64"], fields["f32"]
+    fluid = r64 != 0
+    p64 = (r64 - 1.0)[fluid]
+    res["d2q9_cylinder_2048x1024_f32_vs_f64_2000_steps"] = dict(
+        p_rel_l2=float(((r32 - r64)[fluid]).norm() / p64.norm()),
+        u_rel_l2=float((u32 - u64)[:, fluid].norm() / u64[:, fluid].norm()),
+        u_max_abs=float((u32 - u64)[:, fluid].abs().max()))
+    del fields, r64, u64, r32, u32
     torch.cuda.empty_cache()
     if shedding_steps:
         # the same channel run long enough for periodic shedding: C_L, St
@@ -227,10 +275,11 @@ def other_configs(lbm, torch, steps, shedding_steps):
     return res
 
 
-def serving_bench(n_jobs, step_scale, load, budget_gib, quantum):
+def serving_bench(n_jobs, step_scale, loads, budget_gib, quantum):
     """Continuous-batching serving of the D2Q9 job mix: first all jobs at
     t = 0 (saturated throughput), then a seeded Poisson stream offered at
-    `load` times that throughput; p50/p99 latency from arrival to result."""
+    each of `loads` times that throughput; p50/p99 latency from arrival to
+    result."""
     from paper_1710_02065_amd import serve
     from paper_1710_02065_amd import workloads as W
     be = serve.GpuBackend()
@@ -240,18 +289,24 @@ def serving_bench(n_jobs, step_scale, load, budget_gib, quantum):
     sat_jobs = W.serving_jobs(n_jobs, 5, 1e9, step_scale=step_scale)
     sat = serve.Server(be, budget, quantum).run(sat_jobs).summary()
     work = sum(j["nx"] * j["ny"] * j["steps"] for j in sat_jobs) / len(sat_jobs)
-    rate = load * sat["mlups"] * 1e6 / work
-    jobs = W.serving_jobs(n_jobs, 5, rate, step_scale=step_scale)
-    st = serve.Server(be, budget, quantum).run(jobs).summary()
+    per_load = {}
+    for load in loads:
+        rate = load * sat["mlups"] * 1e6 / work
+        jobs = W.serving_jobs(n_jobs, 5, rate, step_scale=step_scale)
+        st = serve.Server(be, budget, quantum).run(jobs).summary()
+        per_load["%.2f" % load] = dict(
+            arrival_rate_per_s=round(rate, 3), p50_latency_s=round(st["p50_latency_s"], 4),
+            p99_latency_s=round(st["p99_latency_s"], 4), p50_queue_s=round(st["p50_queue_s"], 4),
+            p99_queue_s=round(st["p99_queue_s"], 4), mlups=round(st["mlups"], 1),
+            peak_resident_gib=round(st["peak_bytes"] / 2 ** 30, 3))
     return dict(
         workload="D2Q9 job mix: half cylinder channels, half acoustic pulses, sides U{256..2048}, "
                  "Ma U[0.05, 0.3], steps U{2000..20000} x %g, half FP32 / half FP16-shifted "
                  "storage, Poisson arrivals (seed 5)" % step_scale,
-        jobs=n_jobs, offered_load=load, arrival_rate_per_s=round(rate, 3),
-        p50_latency_s=round(st["p50_latency_s"], 4), p99_latency_s=round(st["p99_latency_s"], 4),
-        p50_queue_s=round(st["p50_queue_s"], 4), mlups=round(st["mlups"], 1),
-        saturated_mlups=round(sat["mlups"], 1), budget_gib=budget_gib, quantum_steps=quantum,
-        peak_resident_gib=round(st["peak_bytes"] / 2 ** 30, 3))
+        jobs=n_jobs, saturated_mlups=round(sat["mlups"], 1),
+        saturated_p50_latency_s=round(sat["p50_latency_s"], 4),
+        saturated_p99_latency_s=round(sat["p99_latency_s"], 4),
+        budget_gib=budget_gib, quantum_steps=quantum, offered_load=per_load)
 
 
 def main():
@@ -273,7 +328,8 @@ def main():
                     default=[500, 1000, 2000, 5000])
     ap.add_argument("--serve-jobs", type=int, default=48)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
-    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-loads", type=lambda s: [float(x) for x in s.split(",")],
+                    default=[0.5, 0.8, 1.0])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-quantum", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -389,7 +445,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving: %d jobs, step scale %g" % (args.serve_jobs, args.serve_step_scale))
-        out["serving"] = serving_bench(args.serve_jobs, args.serve_step_scale, args.serve_load,
+        out["serving"] = serving_bench(args.serve_jobs, args.serve_step_scale, args.serve_loads,
                                        args.serve_budget_gib, args.serve_quantum)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -75,8 +75,9 @@ enum { LBM_PERIODIC = 0, LBM_FREESLIP = 1, LBM_OUTFLOW = 2 };
  *   INLET: holds f^{eqH}(rho0, U u_dir (1 + inlet_noise r)) with r uniform
  *          in [-1, 1) per component, r = (z >> 40) * 2^-23 - 1 where z is the
  *          k-th SplitMix64 output for `seed` (Steele, Lea & Flood 2014),
- *          k = ((t*2 + level)*N_level + cell)*3 + component, t = time index
- *          (on that level) of the state being produced. */
+ *          k = ((t*M + level)*N_level + cell)*3 + component, t = time index
+ *          (on that level) of the state being produced, M = the number of
+ *          levels of the context, at least 2. */
 enum { LBM_FLUID = 0, LBM_SOLID = 1, LBM_INLET = 2 };
 
 /* status codes */
@@ -89,6 +90,10 @@ enum {
   LBM_ESTATE = -5,      /* call out of order (e.g. step before init) */
   LBM_EUNSUPPORTED = -6 /* valid request this build does not implement */
 };
+
+/* levels of a refined context: level 0 plus up to four nested 2:1 boxes
+ * (the paper's setups use four and five levels, Sec. III and IV) */
+#define LBM_MAX_LEVELS 5
 
 /* flags */
 #define LBM_ALLOW_HIGH_MA 0x1u /* accept Ma > 0.6 (beyond the stable range
@@ -118,13 +123,20 @@ typedef struct lbm_config {
   double chi_max;        /* sponge strength maximum, 0 <= chi_max < 4 tau */
   double rho_ref;        /* sponge reference density */
   double u_ref[3];       /* sponge reference velocity */
-  int64_t refine_lo[3];  /* refined coarse-node box [lo, hi]; lo == hi == 0 */
-  int64_t refine_hi[3];  /*   on every axis means no refinement */
+  int64_t refine_lo[3];  /* box [lo, hi] of level 1 in level-0 node       */
+  int64_t refine_hi[3];  /*   coordinates; lo == hi == 0 on every axis: no
+                            refinement */
   uint64_t seed;         /* inlet noise seed */
   double inlet_noise;    /* relative inlet velocity noise amplitude */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
   uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER */
   uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
+  int32_t nest_count;    /* further nested boxes, 0 .. LBM_MAX_LEVELS - 2
+                            (needs refine_lo/hi) */
+  int32_t nest_reserved; /* 0 */
+  int64_t nest_lo[LBM_MAX_LEVELS - 2][3]; /* box k: level k + 2 covers the   */
+  int64_t nest_hi[LBM_MAX_LEVELS - 2][3]; /*   box [lo, hi] of level k + 1,
+                                             in level k + 1 node coordinates */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -142,8 +154,12 @@ size_t lbm_required_bytes(const lbm_config* cfg);
  * (nu = cs^2 (tau - 1/2) must be positive, Sec. II.A); chi_max >= 4 tau on
  * any level (the stability bound of Sec. II.C); ma > 0.6 without
  * LBM_ALLOW_HIGH_MA; unknown lattice or storage; grids above 2^31 - 1 cells;
- * a refinement box that is not at least 4 coarse cells away from every
- * non-periodic face or is smaller than 4 cells per axis.  No device memory
+ * a refinement box that is smaller than 4 cells per axis or not at least 4
+ * cells inside its parent level (inside [4, n - 5]; for level 1 this also
+ * keeps it 4 cells from every face), or that overlaps an absorbing layer.
+ * Each level l + 1 covers its box with half the spacing of level l
+ * (2 (hi - lo) + 1 nodes per axis) and tau_(l+1) = (4 tau_l - 1) / 2, and
+ * advances two steps per step of level l (Sec. II.B, eq. convective).  No device memory
  * is allocated here: the first lbm_init allocates it unless lbm_bind_memory
  * was called before.  *out receives the context. */
 int lbm_create(const lbm_config* cfg, lbm_ctx** out);
@@ -153,7 +169,7 @@ int lbm_create(const lbm_config* cfg, lbm_ctx** out);
  * frees it; the caller keeps it alive until lbm_destroy. */
 int lbm_bind_memory(lbm_ctx* ctx, void* dev_ptr, size_t bytes);
 
-/* Write the post-collision state at t = 0 of `level` (0 = coarse, 1 = fine):
+/* Write the post-collision state at t = 0 of `level` (0 = coarsest):
  *   f*_i = f^{eqH}_i(rho, u) + (1 - 1/tau) f^{neqH}_i(a2_neq = pi_neq, u)
  * (eqs. eqH, neqH).  Device pointers, FP64, structure of arrays over the
  * level's cells: rho [N], u [3][N], pi_neq [6][N] in the order
@@ -165,7 +181,8 @@ int lbm_bind_memory(lbm_ctx* ctx, void* dev_ptr, size_t bytes);
 int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
              const double* pi_neq, const uint8_t* mask);
 
-/* Enqueue n coarse steps (each is two fine substeps on a refined context).
+/* Enqueue n coarse steps (level l + 1 takes two steps per step of level l
+ * on a refined context).
  * Returns after enqueueing.  Kernel-side instability is recorded in a sticky
  * flag reported by lbm_sync / lbm_moments. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
@@ -178,8 +195,8 @@ int lbm_sync(lbm_ctx* ctx);
 int64_t lbm_time(const lbm_ctx* ctx);
 
 /* Cell updates one coarse step performs: all cells of an unrefined grid; on
- * a refined context the swept coarse cells plus twice the swept fine cells
- * (two fine substeps, eq. convective).  Used to report MLUPS. */
+ * a refined context the sum over levels l of 2^l times the cells swept on
+ * level l (eq. convective).  Used to report MLUPS. */
 int64_t lbm_updates_per_step(const lbm_ctx* ctx);
 
 /* Grid shape of a level. */
@@ -222,6 +239,17 @@ int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2);
  * streams.  The summation order is fixed: repeated calls give identical
  * bits.  A context without a mask gives 0. */
 int lbm_force(lbm_ctx* ctx, int level, double* out);
+
+/* Global totals of the stored state of `level` over its updated cells
+ * (every cell but SOLID and COVERED): out[0] = sum (rho - rho0), the mass
+ * relative to rest, and out[1..3] = sum of the momentum j = sum_i f_i xi_i
+ * (eq. moments).  out: FP64 device pointer to 4 values, written on the
+ * context's stream with the same fixed-order reduction as lbm_force (and
+ * the same reduction area: calls on one context must not overlap on
+ * different streams).  In a periodic domain without sponge, inlet or
+ * walls both are invariants of the scheme.  Returns the sticky instability
+ * status as lbm_moments does. */
+int lbm_totals(lbm_ctx* ctx, int level, double* out);
 
 /* Canonical FP64 copy of the stored populations of `level`, [q][N] in the
  * documented direction order, unshifted (device pointers).  Used for

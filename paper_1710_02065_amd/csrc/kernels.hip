@@ -146,7 +146,7 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
       const uint64_t bidx =
-          ((a.t_new * 2ull + (uint64_t)a.level) * (uint64_t)a.ncell + c) * 3ull;
+          ((a.t_new * (uint64_t)a.lstride + (uint64_t)a.level) * (uint64_t)a.ncell + c) * 3ull;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const R r = (R)splitmix_pm1(a.seed, bidx + (uint64_t)k);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
     R chi = (R)0;
     if (a.chi_max != (R)0)
       chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
-    if (a.rec) {
+    if (a.rec || a.recf) {
       CellMoments<R> mo;
       if (chi != (R)0)
         rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
@@ -178,13 +178,23 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       else
         rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
                                            a.uref, base, post, &mo);
-      const int64_t r = record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z);
+      // parent side: moments on the child box's boundary planes
+      const int64_t r =
+          a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
       if (r >= 0) {
         a.rec[r] = mo.drho;
 #pragma unroll
         for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
 #pragma unroll
         for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
+      }
+      // child side: moments in the band the parent's IMPORT nodes filter
+      if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
+        a.recf[c] = mo.drho;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
       }
     } else if (chi != (R)0) {
       rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
@@ -328,26 +338,58 @@ __global__ void k_probe(ProbeArgs a) {
 }
 
 // ------------------------------------------------------------------------
+// Deterministic reductions (force, totals).  Stage one: a fixed grid of
+// kRedBlocks walks the cells with a fixed stride, and each block reduces
+// its threads' NC sums in a fixed LDS tree into one partial; stage two sums
+// the partials in a fixed tree.  The result does not depend on scheduling.
+// ------------------------------------------------------------------------
+template <int NC>
+__device__ __forceinline__ void block_partial(const double (&v)[NC], double* partial) {
+  __shared__ double red[NC][kRedThreads];
+  for (int k = 0; k < NC; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (uint32_t h = kRedThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < NC; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < NC) partial[(uint64_t)blockIdx.x * NC + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kRedThreads) k_reduce_final(const double* partial,
+                                                                double* out) {
+  __shared__ double red[NC][kRedThreads];
+  for (int k = 0; k < NC; ++k) {
+    double v = 0.0;
+    for (uint32_t b = threadIdx.x; b < kRedBlocks; b += kRedThreads)
+      v += partial[(uint64_t)b * NC + k];
+    red[k][threadIdx.x] = v;
+  }
+  __syncthreads();
+  for (uint32_t h = kRedThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < NC; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < NC) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // Force on the SOLID cells by momentum exchange (Ladd; Mei et al. 2002):
 // for every link of a FLUID cell whose pulled source (under the face rules,
 // as in pull_general) is SOLID, the post-collision population f*_j moving
 // into the wall (xi_j = -xi_i) returns reversed, so the wall receives
-// 2 f*_j xi_j.  Stage one: a fixed grid of kForceBlocks walks the cells
-// with a fixed stride and reduces in a fixed LDS tree into one partial per
-// block; stage two sums the partials in a fixed tree.  The result does not
-// depend on scheduling.
-// ------------------------------------------------------------------------
+// 2 f*_j xi_j.
 template <class L, class S>
-__global__ void __launch_bounds__(kForceThreads) k_force(ForceArgs a) {
+__global__ void __launch_bounds__(kRedThreads) k_force(ReduceArgs a) {
   using T = typename S::T;
-  __shared__ double red[3][kForceThreads];
   double F[3] = {0.0, 0.0, 0.0};
   const uint32_t n = a.nx * a.ny * a.nz;
   const T* src = (const T*)a.src;
   const int32_t dims[3] = {(int32_t)a.nx, (int32_t)a.ny, (int32_t)a.nz};
   if (a.mask) {
-    for (uint32_t c = blockIdx.x * kForceThreads + threadIdx.x; c < n;
-         c += kForceBlocks * kForceThreads) {
+    for (uint32_t c = blockIdx.x * kRedThreads + threadIdx.x; c < n;
+         c += kRedBlocks * kRedThreads) {
       const uint8_t m = a.mask[c];
       if ((m & kKindBits) != kFluid || !(m & (kNearSolid | kNearFace))) continue;
       const int32_t p[3] = {(int32_t)(c % a.nx), (int32_t)((c / a.nx) % a.ny),
@@ -378,31 +420,38 @@ __global__ void __launch_bounds__(kForceThreads) k_force(ForceArgs a) {
       });
     }
   }
-  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = F[k];
-  __syncthreads();
-  for (uint32_t h = kForceThreads / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) a.partial[(uint64_t)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+  block_partial<3>(F, a.partial);
 }
 
-__global__ void __launch_bounds__(kForceThreads) k_force_sum(ForceArgs a) {
-  __shared__ double red[3][kForceThreads];
-  for (int k = 0; k < 3; ++k) {
-    double v = 0.0;
-    for (uint32_t b = threadIdx.x; b < kForceBlocks; b += kForceThreads)
-      v += a.partial[(uint64_t)b * 3 + k];
-    red[k][threadIdx.x] = v;
+// Totals of the stored state over the updated cells (every kind but SOLID
+// and COVERED): sum of rho - rho0 and of the momentum j = sum f xi.
+template <class L, class S>
+__global__ void __launch_bounds__(kRedThreads) k_totals(ReduceArgs a) {
+  using R = typename S::R;
+  using T = typename S::T;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const uint32_t n = a.nx * a.ny * a.nz;
+  const T* src = (const T*)a.src;
+  for (uint32_t c = blockIdx.x * kRedThreads + threadIdx.x; c < n;
+       c += kRedBlocks * kRedThreads) {
+    if (a.mask) {
+      const uint8_t k = a.mask[c] & kKindBits;
+      if (k == kSolid || k == kCovered) continue;
+    }
+    R drho = (R)0, j[3] = {(R)0, (R)0, (R)0};
+    static_for<0, L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr Dir v = L::dir(i);
+      const R h = decode<S>(src[(uint64_t)i * a.pstride + c], (R)L::w(i) * (R)a.rho0);
+      drho += h;
+      if constexpr (v.x != 0) j[0] += (R)v.x * h;
+      if constexpr (v.y != 0) j[1] += (R)v.y * h;
+      if constexpr (v.z != 0) j[2] += (R)v.z * h;
+    });
+    acc[0] += (double)drho;
+    for (int k = 0; k < 3; ++k) acc[k + 1] += (double)j[k];
   }
-  __syncthreads();
-  for (uint32_t h = kForceThreads / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h)
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) a.out[threadIdx.x] = red[threadIdx.x][0];
+  block_partial<4>(acc, a.partial);
 }
 
 // canonical FP64 [q][N] <-> native storage
@@ -532,7 +581,7 @@ __global__ void k_roles(RolesArgs a) {
   if (c >= n) return;
   const uint32_t p[3] = {c % a.nx, (c / a.nx) % a.ny, c / (a.nx * a.ny)};
   const uint32_t dims[3] = {a.nx, a.ny, a.nz};
-  if (a.level == 0) {
+  if (a.child) {
     bool inside = true, deep = true;
     for (int ax = 0; ax < a.dim; ++ax) {
       const int32_t v = (int32_t)p[ax];
@@ -540,7 +589,8 @@ __global__ void k_roles(RolesArgs a) {
       if (v < a.lo[ax] + 2 || v > a.hi[ax] - 2) deep = false;
     }
     if (inside) a.mask[c] = deep ? kCovered : kImport;
-  } else {
+  }
+  if (a.ring) {
     bool ring = false;
     for (int ax = 0; ax < a.dim; ++ax)
       if (p[ax] == 0 || p[ax] == dims[ax] - 1) ring = true;
@@ -647,47 +697,38 @@ __global__ void k_ring(RingArgs a) {
     dst[(uint64_t)i * a.pstride + cf] = encode<S>(out[i], (R)L::w(i) * (R)a.rho0);
 }
 
-// IMPORT node state (eq. couplingCF): rho, u of the coincident fine node and
-// the (1/4, 1/2, 1/4)-filtered Pi_neq of its 3^D fine neighbours, all
-// pre-collision moments of the fine level at the common time, pulled from
-// the fine state one fine step earlier; Pi_neq rescaled by
-// alpha_fc = 2 tau_c / tau_f; f = f^{eqH}(rho, u) + (1 - 1/tau_c) f^{neqH}.
+// IMPORT node state (eq. couplingCF): rho, u of the coincident child node
+// and the (1/4, 1/2, 1/4)-filtered Pi_neq of its 3^D child neighbours, all
+// pre-collision moments of the child at the common time, recorded by the
+// child's last sweep; Pi_neq rescaled by alpha_fc = 2 tau_c / tau_f;
+// f = f^{eqH}(rho, u) + (1 - 1/tau_c) f^{neqH}.
 template <class L, class S>
 __global__ void k_import(ImportArgs ia) {
   using R = typename S::R;
   using T = typename S::T;
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= ia.n) return;
-  const SweepArgs<S> a = to_args_dev<S>(ia.fine);
   const uint32_t cc = ia.list[n];
   const int32_t p[3] = {(int32_t)(cc % ia.cnx), (int32_t)((cc / ia.cnx) % ia.cny),
                         (int32_t)(cc / (ia.cnx * ia.cny))};
   int32_t kc[3];
   for (int ax = 0; ax < 3; ++ax) kc[ax] = ax < L::D ? 2 * (p[ax] - ia.lo[ax]) : 0;
+  const uint64_t fn = (uint64_t)ia.fnx * ia.fny * ia.fnz;
+  const R* M = (const R*)ia.recf;
   const R w1[3] = {(R)0.25, (R)0.5, (R)0.25};
   const int oz = L::D == 3 ? 1 : 0;
   R acc[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
-  R drho_c = (R)0, u_c[3] = {(R)0, (R)0, (R)0};
   for (int o2 = -oz; o2 <= oz; ++o2)
     for (int o1 = -1; o1 <= 1; ++o1)
       for (int o0 = -1; o0 <= 1; ++o0) {
-        const uint32_t x = (uint32_t)(kc[0] + o0), y = (uint32_t)(kc[1] + o1),
-                       z = (uint32_t)(kc[2] + o2);
-        const uint32_t c = (z * a.ny + y) * a.nx + x;
-        T raw[L::Q];
-        pull_general<L, S>(a, x, y, z, c, raw);
-        R drho, j[3], P[6], a2[6];
-        stored_moments<L, S>(raw, a.rho0, drho, j, P);
-        const R irho = recip(a.rho0 + drho);
-        const R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
-        noneq_stress<L, R>(drho, j, u, P, a2);
+        const uint64_t c = ((uint64_t)(kc[2] + o2) * ia.fny + (uint64_t)(kc[1] + o1)) * ia.fnx +
+                           (uint64_t)(kc[0] + o0);
         const R w = w1[o0 + 1] * w1[o1 + 1] * (oz ? w1[o2 + 1] : (R)1);
-        for (int q = 0; q < 6; ++q) acc[q] += w * a2[q];
-        if (o0 == 0 && o1 == 0 && o2 == 0) {
-          drho_c = drho;
-          for (int q = 0; q < 3; ++q) u_c[q] = u[q];
-        }
+        for (int q = 0; q < 6; ++q) acc[q] += w * M[(uint64_t)(4 + q) * fn + c];
       }
+  const uint64_t c0 = ((uint64_t)kc[2] * ia.fny + (uint64_t)kc[1]) * ia.fnx + (uint64_t)kc[0];
+  const R drho_c = M[c0];
+  const R u_c[3] = {M[fn + c0], M[2 * fn + c0], L::D == 3 ? M[3 * fn + c0] : (R)0};
   for (int q = 0; q < 6; ++q) acc[q] *= (R)ia.alpha;
   R out[L::Q];
   rebuild_state<L, R>(drho_c, (R)ia.rho0, u_c, acc, (R)ia.omega1, out);
@@ -739,8 +780,10 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
   a.seed = h.seed;
   a.t_new = h.t_new;
   a.level = h.level;
+  a.lstride = h.lstride;
   a.ntiles = 0;
   a.rec = (R*)h.rec;
+  a.recf = (R*)h.recf;
   for (int k = 0; k < 3; ++k) {
     a.rec_off[k] = h.rec_off[k];
     a.rec_dim[k] = h.rec_dim[k];
@@ -893,27 +936,45 @@ hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st) {
 }
 
 template <class L>
-static void force_l(int storage, const ForceArgs& a, hipStream_t st) {
-  const dim3 g(kForceBlocks), b(kForceThreads);
+static void reduce_l(bool totals, int storage, const ReduceArgs& a, hipStream_t st) {
+  const dim3 g(kRedBlocks), b(kRedThreads);
+#define HRLBM_RED(S)                                                          \
+  if (totals)                                                                 \
+    hipLaunchKernelGGL((k_totals<L, S>), g, b, 0, st, a);                     \
+  else                                                                        \
+    hipLaunchKernelGGL((k_force<L, S>), g, b, 0, st, a);
   switch (storage) {
-    case 0: hipLaunchKernelGGL((k_force<L, StoreF64>), g, b, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_force<L, StoreF32>), g, b, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_force<L, StoreF32S>), g, b, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_force<L, StoreF16S>), g, b, 0, st, a); break;
+    case 0: HRLBM_RED(StoreF64) break;
+    case 1: HRLBM_RED(StoreF32) break;
+    case 2: HRLBM_RED(StoreF32S) break;
+    case 3: HRLBM_RED(StoreF16S) break;
   }
+#undef HRLBM_RED
 }
 
-hipError_t launch_force(int lattice, int storage, const ForceArgs& a, hipStream_t st) {
+static hipError_t launch_reduce(bool totals, int lattice, int storage, const ReduceArgs& a,
+                                hipStream_t st) {
   switch (lattice) {
-    case 9: force_l<Lattice<9>>(storage, a, st); break;
-    case 19: force_l<Lattice<19>>(storage, a, st); break;
-    case 27: force_l<Lattice<27>>(storage, a, st); break;
+    case 9: reduce_l<Lattice<9>>(totals, storage, a, st); break;
+    case 19: reduce_l<Lattice<19>>(totals, storage, a, st); break;
+    case 27: reduce_l<Lattice<27>>(totals, storage, a, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_force_sum, dim3(1), dim3(kForceThreads), 0, st, a);
+  if (totals)
+    hipLaunchKernelGGL(k_reduce_final<4>, dim3(1), dim3(kRedThreads), 0, st, a.partial, a.out);
+  else
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kRedThreads), 0, st, a.partial, a.out);
   return hipGetLastError();
+}
+
+hipError_t launch_force(int lattice, int storage, const ReduceArgs& a, hipStream_t st) {
+  return launch_reduce(false, lattice, storage, a, st);
+}
+
+hipError_t launch_totals(int lattice, int storage, const ReduceArgs& a, hipStream_t st) {
+  return launch_reduce(true, lattice, storage, a, st);
 }
 
 hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st) {

@@ -159,6 +159,7 @@ struct SweepArgs {
   uint64_t seed;
   uint64_t t_new;        // time index of the state being produced
   int32_t level;
+  uint32_t lstride;      // inlet-noise counter blocks per time index
   uint32_t ntiles;
   // refinement: pre-collision moments of the coarse nodes on the patch
   // boundary planes are recorded into rec (10 components, SoA over the
@@ -168,7 +169,28 @@ struct SweepArgs {
   uint32_t rec_dim[3];
   uint32_t rec_n;
   int32_t box_lo[3], box_hi[3];
+  // refinement, child side: pre-collision moments of the nodes in the band
+  // the parent's IMPORT nodes filter are recorded into recf (10 components,
+  // SoA over all ncell nodes of this level); nullptr disables it
+  R* recf;
 };
+
+// Band of a child level whose pre-collision moments its parent's IMPORT
+// nodes filter: the parent's IMPORT shell [lo+1, hi-1] lies on child index 2
+// and n - 3 of each axis, and the 3-point filter reaches one node further
+// either way, so the band is every node inside [1, n - 2] on the active axes
+// with index 1, 2, 3, n - 4, n - 3 or n - 2 on at least one of them.
+template <int D>
+__host__ __device__ inline bool in_import_band(uint32_t x, uint32_t y, uint32_t z, uint32_t nx,
+                                               uint32_t ny, uint32_t nz) {
+  const uint32_t p[3] = {x, y, z}, n[3] = {nx, ny, nz};
+  bool edge = false;
+  for (int a = 0; a < D; ++a) {
+    if (p[a] < 1 || p[a] + 2 > n[a]) return false;
+    if (p[a] <= 3 || p[a] + 4 >= n[a]) edge = true;
+  }
+  return edge;
+}
 
 // Index into the record box of a coarse node on a patch boundary plane, or
 // -1 if the node is not recorded.  The record box spans [lo - 1, hi + 1] on

@@ -25,6 +25,7 @@ struct SweepHost {
   int32_t face[6], sponge[6];
   uint64_t seed, t_new;
   int32_t level;
+  uint32_t lstride;  // inlet-noise counter blocks per time index (>= 2)
   bool general;  // false: all periodic, no mask, no sponge
   // refinement record of coarse pre-collision moments (nullptr: off)
   void* rec;
@@ -32,15 +33,17 @@ struct SweepHost {
   uint32_t rec_dim[3];
   uint32_t rec_n;
   int32_t box_lo[3], box_hi[3];
+  // child-side record of the import band (nullptr: off)
+  void* recf;
 };
 
-// Mark the refinement roles in a level's mask: on the coarse level, IMPORT
-// on the shell of [lo+1, hi-1] and COVERED inside it; on the fine level,
-// RING on the outer shell.
+// Mark the refinement roles in a level's mask: with a parent, RING on the
+// outer shell; with a child covering [lo, hi], IMPORT on the shell of
+// [lo+1, hi-1] and COVERED inside it.
 struct RolesArgs {
   uint8_t* mask;
   uint32_t nx, ny, nz;
-  int32_t level, dim;
+  int32_t ring, child, dim;
   int32_t lo[3], hi[3];
 };
 
@@ -85,13 +88,15 @@ struct RingArgs {
   uint64_t pstride;
 };
 
-// IMPORT nodes of the coarse level rebuilt from the fine state.
+// IMPORT nodes of a parent level rebuilt from the child's recorded
+// pre-collision moments (band record, 10 components over the child's nodes).
 struct ImportArgs {
   const uint32_t* list;
   uint32_t n;
   uint32_t cnx, cny;
   int32_t lo[3];
-  SweepHost fine;  // src: fine post-collision state one fine step earlier
+  const void* recf;
+  uint32_t fnx, fny, fnz;
   double alpha, omega1, rho0;
   void* dst;
   uint64_t pstride;
@@ -141,12 +146,13 @@ struct ProbeArgs {
   double rho0;
 };
 
-// Momentum-exchange force: kForceBlocks partial sums (3 doubles each) in
-// `partial`, the total in out[3].
-constexpr uint32_t kForceBlocks = 1024, kForceThreads = 256;
-struct ForceArgs {
+// Deterministic reductions over a level (momentum-exchange force, totals):
+// kRedBlocks partial sums of up to kRedMax doubles each in `partial`, the
+// result in out.
+constexpr uint32_t kRedBlocks = 1024, kRedThreads = 256, kRedMax = 4;
+struct ReduceArgs {
   const void* src;
-  const uint8_t* mask;  // nullptr: no SOLID cells, the force is zero
+  const uint8_t* mask;  // nullptr: all cells fluid (no SOLID cells)
   double* partial;
   double* out;
   uint32_t nx, ny, nz;
@@ -199,7 +205,8 @@ hipError_t launch_moments(int lattice, int storage, const MomentArgs& a,
                           uint32_t n, hipStream_t st);
 hipError_t launch_accum(int lattice, int storage, const AccumArgs& a, uint32_t n,
                         hipStream_t st);
-hipError_t launch_force(int lattice, int storage, const ForceArgs& a, hipStream_t st);
+hipError_t launch_force(int lattice, int storage, const ReduceArgs& a, hipStream_t st);
+hipError_t launch_totals(int lattice, int storage, const ReduceArgs& a, hipStream_t st);
 hipError_t launch_probe(int lattice, int storage, const ProbeArgs& a,
                         uint32_t n, hipStream_t st);
 hipError_t launch_get_pop(int lattice, int storage, const PopArgs& a,

@@ -136,6 +136,11 @@ int validate(const lbm_config* cfg) {
   if (c.chi_max >= 4.0 * c.tau)
     return set_error(LBM_EINVAL, "chi_max = %g >= 4 tau = %g (Sec. II.C stability bound)",
                      c.chi_max, 4.0 * c.tau);
+  if (c.nest_count < 0 || c.nest_count > LBM_MAX_LEVELS - 2)
+    return set_error(LBM_EINVAL, "nest_count %d outside [0, %d]", c.nest_count,
+                     LBM_MAX_LEVELS - 2);
+  if (c.nest_count > 0 && !refined(c))
+    return set_error(LBM_EINVAL, "nested boxes need the level-1 box refine_lo/hi");
   if (refined(c)) return validate_refinement(c);
   return LBM_OK;
 }
@@ -155,8 +160,8 @@ static void level_layout(Level& L, int lattice, int storage) {
 
 void plan_layout(lbm_ctx* ctx) {
   const lbm_config& c = ctx->cfg;
-  // status words first, then the partial sums of lbm_force
-  size_t off = 256 + align_up(sizeof(double) * 3 * kForceBlocks, 256);
+  // status words first, then the partial sums of the reductions
+  size_t off = 256 + align_up(sizeof(double) * kRedMax * kRedBlocks, 256);
   for (int l = 0; l < ctx->nlevels; ++l) {
     Level& L = ctx->lv[l];
     level_layout(L, c.lattice, c.storage);
@@ -201,7 +206,7 @@ static int make_levels(lbm_ctx* ctx) {
     L0.sponge[f] = c.sponge_width[f];
   }
   L0.chi_max = c.chi_max;
-  if (refined(c)) return make_fine_level(ctx);
+  if (refined(c)) return make_levels_refined(ctx);
   return LBM_OK;
 }
 
@@ -331,6 +336,7 @@ SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
   h.seed = c.seed;
   h.t_new = t_new;
   h.level = L.level;
+  h.lstride = ctx->nlevels > 2 ? (uint32_t)ctx->nlevels : 2u;
   h.general = general;
   return h;
 }
@@ -635,7 +641,7 @@ int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2) {
   return LBM_OK;
 }
 
-int lbm_force(lbm_ctx* ctx, int level, double* out) {
+static int reduce_level(lbm_ctx* ctx, int level, double* out, bool totals) {
   int rc = check_ready(ctx);
   if (rc != LBM_OK) return rc;
   if (level < 0 || level >= ctx->nlevels || !out)
@@ -643,7 +649,7 @@ int lbm_force(lbm_ctx* ctx, int level, double* out) {
   rc = ensure_device(ctx);
   if (rc != LBM_OK) return rc;
   const Level& L = ctx->lv[level];
-  ForceArgs a{};
+  ReduceArgs a{};
   a.src = L.buf[L.cur];
   a.mask = L.has_mask ? L.mask : nullptr;
   a.partial = ctx->reduce;
@@ -654,8 +660,20 @@ int lbm_force(lbm_ctx* ctx, int level, double* out) {
   a.pstride = L.pstride;
   for (int f = 0; f < 6; ++f) a.face[f] = L.face[f];
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_force(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
-  if (e != hipSuccess) return hip_error(e, "force launch");
+  hipError_t e = totals ? launch_totals(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream)
+                        : launch_force(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, totals ? "totals launch" : "force launch");
+  return LBM_OK;
+}
+
+int lbm_force(lbm_ctx* ctx, int level, double* out) {
+  return reduce_level(ctx, level, out, false);
+}
+
+int lbm_totals(lbm_ctx* ctx, int level, double* out) {
+  int rc = reduce_level(ctx, level, out, true);
+  if (rc != LBM_OK) return rc;
+  if (ctx->unstable) return set_error(LBM_EUNSTABLE, "non-finite or non-positive density seen");
   return LBM_OK;
 }
 

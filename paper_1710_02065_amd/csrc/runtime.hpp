@@ -40,19 +40,23 @@ struct Refinement;  // two-level coupling state (refine.hip)
 
 }  // namespace hrlbm
 
+namespace hrlbm {
+constexpr int kMaxLevels = LBM_MAX_LEVELS;
+}  // namespace hrlbm
+
 struct lbm_ctx {
   lbm_config cfg{};
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture_stream = nullptr;
   int nlevels = 1;
-  hrlbm::Level lv[2];
+  hrlbm::Level lv[hrlbm::kMaxLevels];
   double uin[3] = {0, 0, 0};
   char* mem = nullptr;
   bool owns_mem = false;
   size_t total_bytes = 0;
   int* status = nullptr;
-  double* reduce = nullptr;  // kForceBlocks x 3 partial sums
+  double* reduce = nullptr;  // kRedBlocks x kRedMax partial sums
   bool status_cleared = false;
   bool unstable = false;
   bool initialised = false;
@@ -60,8 +64,8 @@ struct lbm_ctx {
   int64_t t = 0;
   int block = 256;
   std::map<int, hrlbm::GraphEntry> graphs;
-  hrlbm::Refinement* ref = nullptr;
-  size_t ref_off = 0, ref_bytes = 0;
+  // interface l couples level l (parent) and level l + 1 (child)
+  hrlbm::Refinement* ref[hrlbm::kMaxLevels - 1] = {};
   ~lbm_ctx();
 };
 
@@ -92,7 +96,6 @@ int tuned_block(const lbm_ctx* ctx);
 
 // two-level refinement (refine.hip)
 int validate_refinement(const lbm_config& c);
-int make_fine_level(lbm_ctx* ctx);
 size_t plan_interface_layout(lbm_ctx* ctx, size_t off);
 void assign_interface_pointers(lbm_ctx* ctx);
 int refined_init_level(lbm_ctx* ctx, int level, const double* rho, const double* u,
@@ -101,6 +104,7 @@ int refined_after_init(lbm_ctx* ctx);
 int64_t refined_updates_per_step(const lbm_ctx* ctx);
 int refined_after_set(lbm_ctx* ctx, int level);
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st);
+int make_levels_refined(lbm_ctx* ctx);
 void free_refinement(lbm_ctx* ctx);
 
 }  // namespace hrlbm

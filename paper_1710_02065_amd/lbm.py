@@ -22,6 +22,7 @@ LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER = 0x1, 0x2, 0x4
+LBM_MAX_LEVELS = 5
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S}
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
@@ -30,7 +31,7 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
-           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_get_populations", "lbm_set_populations",
+           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_get_populations", "lbm_set_populations",
            "lbm_step_batch", "lbm_autotune", "lbm_destroy", "lbm_lattice_table",
            "lbm_last_error"]
 
@@ -47,6 +48,9 @@ class lbm_config(C.Structure):
         ("refine_lo", C.c_int64 * 3), ("refine_hi", C.c_int64 * 3),
         ("seed", C.c_uint64), ("inlet_noise", C.c_double),
         ("stream", C.c_void_p), ("flags", C.c_uint32), ("block", C.c_uint32),
+        ("nest_count", C.c_int32), ("nest_reserved", C.c_int32),
+        ("nest_lo", (C.c_int64 * 3) * (LBM_MAX_LEVELS - 2)),
+        ("nest_hi", (C.c_int64 * 3) * (LBM_MAX_LEVELS - 2)),
     ]
 
 
@@ -85,6 +89,7 @@ def lib():
         L.lbm_moments.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_probe.argtypes = [vp, C.c_int, vp, C.c_int, dp]
         L.lbm_force.argtypes = [vp, C.c_int, dp]
+        L.lbm_totals.argtypes = [vp, C.c_int, dp]
         L.lbm_accumulate.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_get_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
@@ -173,6 +178,10 @@ def lbm_force(ctx, level, out):
     return _check(lib().lbm_force(ctx, level, _ptr(out)))
 
 
+def lbm_totals(ctx, level, out):
+    return _check(lib().lbm_totals(ctx, level, _ptr(out)))
+
+
 def lbm_get_populations(ctx, level, out):
     return _check(lib().lbm_get_populations(ctx, level, _ptr(out)))
 
@@ -212,7 +221,10 @@ def make_config(lattice=LBM_D3Q19, shape=(64, 64, 64), tau=0.6, storage="f32", r
                 ma=0.0, u_dir=(1.0, 0.0, 0.0), face_bc=(LBM_PERIODIC,) * 6,
                 sponge_width=(0,) * 6, chi_max=0.0, rho_ref=1.0, u_ref=(0.0, 0.0, 0.0),
                 refine_lo=(0, 0, 0), refine_hi=(0, 0, 0), seed=0, inlet_noise=0.0,
-                stream=None, flags=0, block=0, device=0):
+                stream=None, flags=0, block=0, device=0, nest=()):
+    """Configuration block.  refine_lo/hi: box of level 1 in level-0
+    coordinates; nest: further boxes [(lo, hi), ...], box k in the node
+    coordinates of level k + 1."""
     cfg = lbm_config_init()
     cfg.lattice = lattice
     cfg.storage = STORAGE[storage] if isinstance(storage, str) else storage
@@ -230,6 +242,13 @@ def make_config(lattice=LBM_D3Q19, shape=(64, 64, 64), tau=0.6, storage="f32", r
     cfg.seed, cfg.inlet_noise = seed, inlet_noise
     cfg.stream = stream
     cfg.flags, cfg.block = flags, block
+    nest = list(nest)
+    if len(nest) > LBM_MAX_LEVELS - 2:
+        raise ValueError("at most %d nested boxes" % (LBM_MAX_LEVELS - 2))
+    cfg.nest_count = len(nest)
+    for k, (lo, hi) in enumerate(nest):
+        cfg.nest_lo[k][:] = (list(lo) + [0, 0, 0])[:3]
+        cfg.nest_hi[k][:] = (list(hi) + [0, 0, 0])[:3]
     return cfg
 
 
@@ -321,6 +340,14 @@ class Simulation:
         if out is None:
             out = self.torch.empty(3, dtype=self.torch.float64, device=self.device)
         lbm_force(self.ctx, level, out)
+        return out
+
+    def totals(self, level=0, out=None):
+        """(sum of rho - rho0, momentum x, y, z) over the updated cells, 4
+        FP64 on the device."""
+        if out is None:
+            out = self.torch.empty(4, dtype=self.torch.float64, device=self.device)
+        lbm_totals(self.ctx, level, out)
         return out
 
     def accumulate(self, sum1, sum2=None, level=0):

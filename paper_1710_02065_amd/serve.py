@@ -59,6 +59,7 @@ class Stats:
                     p50_latency_s=self.pct(self.latencies, 50),
                     p99_latency_s=self.pct(self.latencies, 99),
                     p50_queue_s=self.pct(self.queue_delays, 50),
+                    p99_queue_s=self.pct(self.queue_delays, 99),
                     mlups=self.cell_updates / self.makespan / 1e6 if self.makespan > 0 else 0.0,
                     makespan_s=self.makespan, peak_bytes=self.peak_bytes, quanta=self.quanta)
 

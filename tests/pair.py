@@ -93,3 +93,23 @@ def refined_pair(case):
 
 def refined_sim(case, storage="f64", **kw):
     return gpu_sim(case, storage, refine_lo=tuple(case["lo"]), refine_hi=tuple(case["hi"]), **kw)
+
+
+def multilevel_pair(case):
+    """Oracle MultiLevelGrid for a case with lo, hi (level-1 box) and nest
+    (further boxes), optional masks per level."""
+    nx, ny, nz = case["shape"]
+    boxes = [(case["lo"], case["hi"])] + list(case.get("nest", ()))
+    return O.MultiLevelGrid(case["q"], nx, ny, nz, boxes=boxes,
+                            tau=case.get("tau", 0.6), rho0=case.get("rho0", 1.0),
+                            u_in=inlet_velocity(case), face_bc=case.get("face_bc", (0,) * 6),
+                            sponge_width=case.get("sponge_width", (0,) * 6),
+                            chi_max=case.get("chi_max", 0.0), rho_ref=case.get("rho_ref", 1.0),
+                            u_ref=case.get("u_ref", (0.0, 0.0, 0.0)), seed=case.get("seed", 0),
+                            inlet_noise=case.get("inlet_noise", 0.0),
+                            masks=case.get("masks"), full_order=case.get("full", False))
+
+
+def multilevel_sim(case, storage="f64", **kw):
+    return gpu_sim(case, storage, refine_lo=tuple(case["lo"]), refine_hi=tuple(case["hi"]),
+                   nest=tuple(case.get("nest", ())), **kw)

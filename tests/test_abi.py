@@ -118,3 +118,14 @@ def test_full_order_needs_d2q9_or_d3q27():
     assert "full_order" in lbm.lbm_last_error().lower()
     assert required(lattice=27, shape=(16, 16, 16), flags=lbm.LBM_FULL_ORDER) > 0
     assert required(lattice=9, shape=(16, 16, 1), flags=lbm.LBM_FULL_ORDER) > 0
+
+
+def test_nested_box_validation():
+    base = dict(lattice=9, shape=(48, 40, 1), refine_lo=(10, 8, 0), refine_hi=(36, 30, 0))
+    assert lbm.lbm_required_bytes(lbm.make_config(nest=[((4, 4, 0), (20, 20, 0))], **base)) > 0
+    # level 1 has 53 x 45 nodes: a box must lie in [4, n - 5]
+    bad = lbm.make_config(nest=[((4, 4, 0), (49, 20, 0))], **base)
+    assert lbm.lbm_required_bytes(bad) == 0
+    assert "box 1" in lbm.lbm_last_error()
+    cfg = lbm.make_config(lattice=9, shape=(48, 40, 1), nest=[((4, 4, 0), (20, 20, 0))])
+    assert lbm.lbm_required_bytes(cfg) == 0

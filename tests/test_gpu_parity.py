@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from paper_1710_02065_amd import workloads as W
+import oracle as O
 from tests.pair import gpu_sim, log, normwise, oracle_grid, run_both
 
 torch = pytest.importorskip("torch")
@@ -453,3 +454,37 @@ def test_accumulate_matches_oracle_moments():
     assert normwise(s1.cpu().numpy(), o1) <= 1e-11
     assert normwise(s2.cpu().numpy(), o2) <= 1e-11
     assert np.all(s1.cpu().numpy()[~fluid] == 0.0)
+
+
+def test_totals_match_oracle_and_are_conserved():
+    """Global mass (relative to rest) and momentum against the oracle's sums
+    in FP64; in a periodic run they stay constant (FP64: to rounding; FP32:
+    within the storage rounding of the deviations)."""
+    case = channel_case(19)
+    rho, u = W.uniform_perturbed(case["shape"], 0.1, (1, 0, 0), seed=13, rel_noise=2e-2, d=3)
+    sim = gpu_sim(case, "f64")
+    log("totals channel")
+    sim.init(rho, u, None, case["mask"])
+    g = oracle_grid(case).init(rho, u)
+    sim.step(11)
+    g.step(11)
+    T = sim.totals().cpu().numpy()
+    sim.sync()
+    xi, _, _ = O.lattice(19)
+    upd = case["mask"] != W.SOLID
+    want = np.concatenate([[g.f[:, upd].sum() - upd.sum() * 1.0],
+                           (g.f[:, upd].sum(axis=1)[:, None] * xi).sum(axis=0)])
+    scale = np.abs(g.f[:, upd]).sum()
+    np.testing.assert_allclose(T, want, rtol=0, atol=64 * np.finfo(float).eps * scale)
+    for storage, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        shape = RAGGED[27]
+        rho, u, p = W.random_state(shape, seed=14, d=3, u_amp=0.05)
+        s = gpu_sim(dict(q=27, shape=shape, tau=0.6), storage)
+        log("totals periodic %s" % storage)
+        s.init(rho, u, p)
+        t0 = s.totals().cpu().numpy()
+        s.step(50)
+        t1 = s.totals().cpu().numpy()
+        s.sync()
+        N = np.prod(shape)
+        assert np.abs(t1 - t0).max() <= tol * N

@@ -1,4 +1,5 @@
-"""Two-level 2:1 refinement on the GPU against the refined oracle (Sec. II.B):
+"""2:1 refinement on the GPU against the refined oracles (Sec. II.B), two
+levels and nested chains of three and four:
 coarse sweep with interface-moment record, two fine sweeps, RING fills at
 t + 1/2 and t + 1, IMPORT by filtered fine moments.  FP64 build within 1e-12
 normwise on both levels."""
@@ -121,3 +122,79 @@ def test_refined_set_populations_unsupported():
         sim.set_populations(f, 0)
     assert e.value.code == lbm.LBM_EUNSUPPORTED
     assert sim.updates_per_step == (32 * 32 - 11 * 11) + 2 * (25 * 25 - 4 * 24)
+
+
+# ------------------------------------------------------------------------
+# More than two levels: the coupling at every interface of a nested chain
+# ------------------------------------------------------------------------
+def run_multilevel(case, steps, storage="f64", seed=1):
+    from tests.pair import multilevel_pair, multilevel_sim
+    og = multilevel_pair(case)
+    d = 2 if case["q"] == 9 else 3
+    fields = [W.random_state(g.shape, seed=seed + l, d=d, u_amp=0.03, rho_amp=0.01,
+                             pi_amp=5e-4) for l, g in enumerate(og.grids)]
+    masks = case.get("masks") or [None] * len(og.grids)
+    log("multilevel %s q=%d levels=%d shapes=%s storage=%s steps=%d"
+        % (case.get("name"), case["q"], len(og.grids), [g.shape for g in og.grids], storage,
+           steps))
+    sim = multilevel_sim(case, storage)
+    for l, f in enumerate(fields):
+        sim.init(*f, mask=masks[l], level=l)
+    sim.step(steps)
+    pops = [sim.populations(l).cpu().numpy() for l in range(len(og.grids))]
+    sim.sync()
+    for l, f in enumerate(fields):
+        og.init(l, *f)
+    og.step(steps)
+    return pops, og, sim
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_three_level_parity_f64(q):
+    if q == 9:
+        case = dict(name="ml2d", q=9, shape=(48, 40, 1), lo=(10, 8, 0), hi=(36, 30, 0),
+                    nest=[((12, 10, 0), (34, 30, 0))], tau=0.57)
+    else:
+        case = dict(name="ml3d", q=q, shape=(24, 22, 20), lo=(5, 5, 5), hi=(17, 16, 15),
+                    nest=[((6, 6, 6), (16, 15, 14))], tau=0.55)
+    pops, og, sim = run_multilevel(case, 4)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2  # COVERED nodes are never updated
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+    assert sim.updates_per_step == sum(
+        int(((og.crole[l] == 0) & (og.ring[l] == 0)).sum()) << l for l in range(3))
+
+
+def test_four_level_2d_parity_f64():
+    case = dict(name="ml4", q=9, shape=(40, 36, 1), lo=(8, 8, 0), hi=(30, 28, 0),
+                nest=[((8, 8, 0), (36, 32, 0)), ((10, 10, 0), (46, 40, 0))], tau=0.6)
+    pops, og, _ = run_multilevel(case, 3)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+
+
+def test_three_level_open_boundaries_parity_f64():
+    """Inlet disc with noise (counter blocks of three levels), sponge and
+    free-slip/outflow faces on level 0, two nested boxes in the middle."""
+    shape = (34, 26, 26)
+    mask = W.jet_inlet_mask(*shape, D=6)
+    case = dict(name="ml-open", q=19, shape=shape, lo=(7, 6, 6), hi=(21, 19, 19),
+                nest=[((6, 6, 6), (20, 20, 20))], tau=0.52, ma=0.2, seed=3,
+                inlet_noise=0.02, face_bc=(2, 2, 1, 1, 2, 2), sponge_width=(0, 8, 0, 0, 0, 4),
+                chi_max=0.3, masks=[mask, None, None])
+    pops, og, _ = run_multilevel(case, 5)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+
+
+def test_three_level_f32_tracks_oracle():
+    """FP32 storage over three levels stays within the derived bound of the
+    FP64 oracle (the two-level shear-wave argument, per level)."""
+    case = dict(name="ml-f32", q=9, shape=(48, 40, 1), lo=(10, 8, 0), hi=(36, 30, 0),
+                nest=[((12, 10, 0), (34, 30, 0))], tau=0.6)
+    pops, og, sim = run_multilevel(case, 40, "f32")
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= 2e-6 * 40 ** 0.5, l

@@ -140,8 +140,13 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
                                        base, post);
   } else {
     const uint8_t m = a.mask ? a.mask[c] : kFluid;
+    // the interior pull is issued before the mask decides: its addresses
+    // are valid for every cell, and the loads overlap the mask's latency
+    pull_periodic<L, S>(a, c, x, y, z, raw);
     const uint8_t kind = m & kKindBits;
     if (kind == kSolid || kind >= kCovered) return;
+    // one rebuild for every kind of cell keeps the kernel's code compact
+    Coeffs<L, R> cf;
     if (kind == kInlet) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
@@ -154,55 +159,43 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       }
       if (L::D == 2) u[2] = (R)0;
       const R zero6[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
-      rebuild_state<L, R>((R)0, a.rho0, u, zero6, (R)0, post);
-      static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const R wr = (R)L::w(i) * a.rho0;
-        __builtin_nontemporal_store(encode<S>(post[i], wr), &a.dst[(uint64_t)i * P + c]);
-      });
-      return;
-    }
-    if (!a.mask || (m & (kNearFace | kNearSolid)))
-      pull_general<L, S>(a, x, y, z, c, raw);
-    else
-      pull_periodic<L, S>(a, c, x, y, z, raw);
-    stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
-    R chi = (R)0;
-    if (a.chi_max != (R)0)
-      chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
-    if (a.rec || a.recf) {
-      CellMoments<R> mo;
-      if (chi != (R)0)
-        rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
-                                          a.uref, base, post, &mo);
-      else
-        rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref,
-                                           a.uref, base, post, &mo);
-      // parent side: moments on the child box's boundary planes
-      const int64_t r =
-          a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
-      if (r >= 0) {
-        a.rec[r] = mo.drho;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
-      }
-      // child side: moments in the band the parent's IMPORT nodes filter
-      if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
-        a.recf[c] = mo.drho;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
-      }
-    } else if (chi != (R)0) {
-      rho = collide_moments<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
-                                        base, post);
+      state_coeffs<L, R>((R)0, a.rho0, u, zero6, (R)0, cf);
+      rho = a.rho0;
     } else {
-      rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
-                                         base, post);
+      if (!a.mask || (m & (kNearFace | kNearSolid))) pull_general<L, S>(a, x, y, z, c, raw);
+      stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
+      CellMoments<R> mo;
+      const bool record = a.rec || a.recf;
+      if (m & kInSponge) {
+        const R chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
+        rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
+                                         cf, record ? &mo : nullptr);
+      } else {
+        rho = collide_coeffs<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref,
+                                          a.uref, cf, record ? &mo : nullptr);
+      }
+      if (record) {
+        // parent side: moments on the child box's boundary planes
+        const int64_t r =
+            a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
+        if (r >= 0) {
+          a.rec[r] = mo.drho;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
+        }
+        // child side: moments in the band the parent's IMPORT nodes filter
+        if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
+          a.recf[c] = mo.drho;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
+        }
+      }
     }
+    rebuild_from<L, R>(cf, base, post);
   }
   // stability watchdog: a rare, benign racy store of 1
   if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
@@ -569,6 +562,9 @@ __global__ void k_flags(FlagsArgs a) {
             kSolid)
       flags |= kNearSolid;
   }
+  if (a.chi_max > 0.0 && sponge_chi<double>(a.sponge, a.chi_max, (uint32_t)p[0], (uint32_t)p[1],
+                                             (uint32_t)p[2], a.nx, a.ny, a.nz) > 0.0)
+    flags |= kInSponge;
   a.mask[c] = (uint8_t)((a.mask[c] & kKindBits) | flags);
 }
 

@@ -29,10 +29,11 @@ enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
 // from fine data), RING (fine node rebuilt from coarse data); cells of the
 // three internal kinds are not swept.
 enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2, kCovered = 3, kImport = 4, kRing = 5 };
-// The mask byte holds the kind in its low six bits and two flags computed
-// at initialisation: the cell has a SOLID neighbour, or it lies on a
-// non-periodic face.  Cells with neither flag pull like a periodic grid.
-enum : uint8_t { kKindBits = 0x3F, kNearFace = 0x40, kNearSolid = 0x80 };
+// The mask byte holds the kind in its low three bits and flags computed at
+// initialisation: the cell lies in an absorbing layer (chi > 0), has a SOLID
+// neighbour, or lies on a non-periodic face.  Cells without the last two
+// pull like a periodic grid; cells without the first skip the sponge.
+enum : uint8_t { kKindBits = 0x07, kInSponge = 0x08, kNearFace = 0x40, kNearSolid = 0x80 };
 
 // ------------------------------------------------------------------------
 // Division of 32-bit unsigned numbers below 2^31 by a run-time invariant
@@ -501,14 +502,15 @@ struct CellMoments {
   R drho, u[3], a2[6];
 };
 
-// Collision of one cell (eq. optimizedLB, with eqs. spongeLB/dampingLBM and
-// the modified moments at n = m = 1/2 where chi > 0).  h: pre-collision
-// deviations; out: post-collision deviations.  Returns rho* for the
-// stability watchdog; fills *mo when given.
+// Hermite coefficients of one cell's collision (eq. optimizedLB, with eqs.
+// spongeLB/dampingLBM and the modified moments at n = m = 1/2 where
+// chi > 0): post = (1 - chi) E(rho*, u) + chi E(rho_ref, u_ref) + omega1 N.
+// kSponge = false assumes chi = 0.  Returns rho* for the stability
+// watchdog; fills *mo (pre-collision rho* - rho0, u, a2_neq) when given.
 template <class L, class R, bool kSponge>
-__device__ __forceinline__ R collide_moments(R drho, R j[3], const R P[6], R omega1, R rho0,
-                                             R chi, R rho_ref, const R uref[3], R base,
-                                             R out[L::Q], CellMoments<R>* mo = nullptr) {
+__device__ __forceinline__ R collide_coeffs(R drho, R j[3], const R P[6], R omega1, R rho0,
+                                            R chi, R rho_ref, const R uref[3],
+                                            Coeffs<L, R>& c, CellMoments<R>* mo = nullptr) {
   if constexpr (kSponge) {
     if (chi != (R)0) {
       const R k = recip((R)1 + (R)0.5 * chi);
@@ -530,46 +532,64 @@ __device__ __forceinline__ R collide_moments(R drho, R j[3], const R P[6], R ome
 #pragma unroll
     for (int a = 0; a < 6; ++a) mo->a2[a] = a2[a];
   }
-
-  Coeffs<L, R> c;
-  R a3n[7], a3e[7];
+  R a3n[7];
   recursion3<R>(u, a2, a3n);
-  cube3<R>(rho, u, a3e);
+  cube3<R>(rho, u, c.m3);
+  c.m0 = drho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.m1[a] = j[a];
+  c.m2[0] = j[0] * u[0];
+  c.m2[1] = j[1] * u[1];
+  c.m2[2] = j[2] * u[2];
+  c.m2[3] = j[0] * u[1];
+  c.m2[4] = j[0] * u[2];
+  c.m2[5] = j[1] * u[2];
   if constexpr (kSponge) {
-    // post = (1 - chi) E(rho*, u) + chi E(rho_ref, u_ref) + omega1 N
-    const R e = (R)1 - chi;
-    c.m0 = e * drho + chi * (rho_ref - rho0);
+    if (chi != (R)0) {
+      // (1 - chi) E(rho*, u) + chi E(rho_ref, u_ref)
+      const R e = (R)1 - chi;
+      const R ru[3] = {rho_ref * uref[0], rho_ref * uref[1], rho_ref * uref[2]};
+      R a3r[7];
+      cube3<R>(rho_ref, uref, a3r);
+      c.m0 = e * c.m0 + chi * (rho_ref - rho0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) c.m1[a] = e * j[a] + chi * rho_ref * uref[a];
-    const R ru[3] = {rho_ref * uref[0], rho_ref * uref[1], rho_ref * uref[2]};
-    c.m2[0] = e * j[0] * u[0] + chi * ru[0] * uref[0] + omega1 * a2[0];
-    c.m2[1] = e * j[1] * u[1] + chi * ru[1] * uref[1] + omega1 * a2[1];
-    c.m2[2] = e * j[2] * u[2] + chi * ru[2] * uref[2] + omega1 * a2[2];
-    c.m2[3] = e * j[0] * u[1] + chi * ru[0] * uref[1] + omega1 * a2[3];
-    c.m2[4] = e * j[0] * u[2] + chi * ru[0] * uref[2] + omega1 * a2[4];
-    c.m2[5] = e * j[1] * u[2] + chi * ru[1] * uref[2] + omega1 * a2[5];
-    R a3r[7];
-    cube3<R>(rho_ref, uref, a3r);
+      for (int a = 0; a < 3; ++a) c.m1[a] = e * c.m1[a] + chi * ru[a];
+      c.m2[0] = e * c.m2[0] + chi * ru[0] * uref[0];
+      c.m2[1] = e * c.m2[1] + chi * ru[1] * uref[1];
+      c.m2[2] = e * c.m2[2] + chi * ru[2] * uref[2];
+      c.m2[3] = e * c.m2[3] + chi * ru[0] * uref[1];
+      c.m2[4] = e * c.m2[4] + chi * ru[0] * uref[2];
+      c.m2[5] = e * c.m2[5] + chi * ru[1] * uref[2];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) c.m3[k] = e * a3e[k] + chi * a3r[k] + omega1 * a3n[k];
-  } else {
-    c.m0 = drho;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) c.m1[a] = j[a];
-    c.m2[0] = j[0] * u[0] + omega1 * a2[0];
-    c.m2[1] = j[1] * u[1] + omega1 * a2[1];
-    c.m2[2] = j[2] * u[2] + omega1 * a2[2];
-    c.m2[3] = j[0] * u[1] + omega1 * a2[3];
-    c.m2[4] = j[0] * u[2] + omega1 * a2[4];
-    c.m2[5] = j[1] * u[2] + omega1 * a2[5];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
+      for (int k = 0; k < 7; ++k) c.m3[k] = e * c.m3[k] + chi * a3r[k];
+    }
   }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) c.m2[a] += omega1 * a2[a];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) c.m3[k] += omega1 * a3n[k];
   if constexpr (L::KH > 0)
     high_coeffs<L, R, kSponge>(rho, u, a2, omega1, chi, rho_ref, uref, c);
+  return rho;
+}
+
+// Populations from the Hermite coefficients (`base` added to m0: rho0 when
+// the stored value is f itself, 0 when it is the deviation from rest).
+template <class L, class R>
+__device__ __forceinline__ void rebuild_from(const Coeffs<L, R>& c, R base, R out[L::Q]) {
   R bk[L::K];
   basis_coeffs<L, R>(c.m3, bk);
   rebuild_all<L, R>(c, bk, base, out);
+}
+
+// Collision of one cell: coefficients and rebuild.
+template <class L, class R, bool kSponge>
+__device__ __forceinline__ R collide_moments(R drho, R j[3], const R P[6], R omega1, R rho0,
+                                             R chi, R rho_ref, const R uref[3], R base,
+                                             R out[L::Q], CellMoments<R>* mo = nullptr) {
+  Coeffs<L, R> c;
+  const R rho = collide_coeffs<L, R, kSponge>(drho, j, P, omega1, rho0, chi, rho_ref, uref, c, mo);
+  rebuild_from<L, R>(c, base, out);
   return rho;
 }
 
@@ -585,14 +605,13 @@ __device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi, R
                                         out, mo);
 }
 
-// Deviations of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u) (initial state and
-// inlet cells), rho given as its deviation drho from rho0.
+// Hermite coefficients of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u) (initial
+// state, inlet cells, refinement interfaces), rho given as its deviation
+// drho from rho0.
 template <class L, class R>
-__device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
-                                              const R a2[6], R omega1,
-                                              R out[L::Q]) {
+__device__ __forceinline__ void state_coeffs(R drho, R rho0, const R u[3], const R a2[6],
+                                             R omega1, Coeffs<L, R>& c) {
   const R rho = rho0 + drho;
-  Coeffs<L, R> c;
   c.m0 = drho;
   const R j[3] = {rho * u[0], rho * u[1], rho * u[2]};
 #pragma unroll
@@ -610,9 +629,16 @@ __device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
   for (int k = 0; k < 7; ++k) c.m3[k] = a3e[k] + omega1 * a3n[k];
   if constexpr (L::KH > 0)
     high_coeffs<L, R, false>(rho, u, a2, omega1, (R)0, (R)0, u, c);
-  R bk[L::K];
-  basis_coeffs<L, R>(c.m3, bk);
-  rebuild_all<L, R>(c, bk, (R)0, out);
+}
+
+// Deviations of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u).
+template <class L, class R>
+__device__ __forceinline__ void rebuild_state(R drho, R rho0, const R u[3],
+                                              const R a2[6], R omega1,
+                                              R out[L::Q]) {
+  Coeffs<L, R> c;
+  state_coeffs<L, R>(drho, rho0, u, a2, omega1, c);
+  rebuild_from<L, R>(c, (R)0, out);
 }
 
 // ------------------------------------------------------------------------

@@ -47,12 +47,14 @@ struct RolesArgs {
   int32_t lo[3], hi[3];
 };
 
-// Flag bits of the mask (see kernels.hpp): near a SOLID cell, on a
-// non-periodic face.
+// Flag bits of the mask (see kernels.hpp): in an absorbing layer, near a
+// SOLID cell, on a non-periodic face.
 struct FlagsArgs {
   uint8_t* mask;
   uint32_t nx, ny, nz;
   int32_t face[6];
+  int32_t sponge[6];
+  double chi_max;
 };
 
 // Record box of the coarse moments filled from the initial fields.

@@ -494,7 +494,11 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
     fa.nx = (uint32_t)L.nx;
     fa.ny = (uint32_t)L.ny;
     fa.nz = (uint32_t)L.nz;
-    for (int f = 0; f < 6; ++f) fa.face[f] = L.face[f];
+    for (int f = 0; f < 6; ++f) {
+      fa.face[f] = L.face[f];
+      fa.sponge[f] = L.sponge[f];
+    }
+    fa.chi_max = L.chi_max;
     e = launch_flags(ctx->cfg.lattice, fa, ctx->stream);
     if (e != hipSuccess) return hip_error(e, "flags launch");
   }

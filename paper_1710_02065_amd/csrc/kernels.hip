@@ -32,24 +32,27 @@ __device__ __forceinline__ int dir_rt(int x, int y, int z) {
 }
 
 // ------------------------------------------------------------------------
-// Pull of all populations of cell (x, y, z) under the face rules and the
-// mask (left side of eq. optimizedLB read backwards): the source of
-// population i is x - xi_i, mapped axis by axis (periodic wrap, free-slip
-// reflection with the population mirrored, zero-gradient clamp); a link
-// whose source is SOLID is bounced back halfway from this cell.
+// Pull under the face rules and the mask (left side of eq. optimizedLB read
+// backwards): the source of population i is x - xi_i, mapped axis by axis
+// (periodic wrap, free-slip reflection with the population mirrored,
+// zero-gradient clamp); a link whose source is SOLID is bounced back
+// halfway from this cell.  Applied as corrections to the periodic pull
+// already in raw[]: only the directions whose source crosses a non-periodic
+// face, or (for cells flagged kNearSolid) is SOLID, are loaded again.
 // ------------------------------------------------------------------------
 template <class L, class S>
-__device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
-                                             uint32_t y, uint32_t z, uint32_t c,
-                                             typename S::T raw[L::Q]) {
+__device__ __forceinline__ void pull_fixup(const SweepArgs<S>& a, uint32_t x, uint32_t y,
+                                           uint32_t z, uint32_t c, bool near_solid,
+                                           typename S::T raw[L::Q]) {
   const uint64_t P = a.pstride;
   const uint32_t dims[3] = {a.nx, a.ny, a.nz};
-  static_for<0, L::Q>([&](auto I) {
+  static_for<1, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Dir v = L::dir(i);
     constexpr int vv[3] = {v.x, v.y, v.z};
     int32_t s[3] = {(int32_t)x - v.x, (int32_t)y - v.y, (int32_t)z - v.z};
     bool flip[3] = {false, false, false};
+    bool cross = false;
 #pragma unroll
     for (int ax = 0; ax < L::D; ++ax) {
       if (vv[ax] == 0) continue;
@@ -62,16 +65,17 @@ __device__ __forceinline__ void pull_general(const SweepArgs<S>& a, uint32_t x,
         } else {
           s[ax] = lo ? 0 : n - 1;
           flip[ax] = (bc == kFreeSlip);
+          cross = true;
         }
       }
     }
     const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
-    if (a.mask && (a.mask[src] & kKindBits) == kSolid) {
+    if (near_solid && (a.mask[src] & kKindBits) == kSolid) {
       // halfway bounce-back: the population that left this cell towards
       // the wall comes back reversed (same weight, so the same shift)
       constexpr int o = opposite<L>(i);
       raw[i] = load_pop(a.src + (uint64_t)o * P, c);
-    } else {
+    } else if (cross) {
       int pop = i;
       if (flip[0] || flip[1] || flip[2])
         pop = dir_rt<L>(flip[0] ? -v.x : v.x, flip[1] ? -v.y : v.y,
@@ -139,9 +143,14 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
     rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref,
                                        base, post);
   } else {
-    const uint8_t m = a.mask ? a.mask[c] : kFluid;
-    // the interior pull is issued before the mask decides: its addresses
-    // are valid for every cell, and the loads overlap the mask's latency
+    // a plain tile (wave-uniform, read through the scalar cache) needs no
+    // mask; otherwise the interior pull is issued before the mask decides:
+    // its addresses are valid for every cell, and the loads overlap the
+    // mask's latency
+    const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane(c) >> 6;
+    const bool plain = a.tiles && a.tiles[tile];
+    uint8_t m = kFluid;  // (every level on this path carries a mask)
+    if (!plain) m = a.mask ? a.mask[c] : kFluid;
     pull_periodic<L, S>(a, c, x, y, z, raw);
     const uint8_t kind = m & kKindBits;
     if (kind == kSolid || kind >= kCovered) return;
@@ -162,19 +171,18 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       state_coeffs<L, R>((R)0, a.rho0, u, zero6, (R)0, cf);
       rho = a.rho0;
     } else {
-      if (!a.mask || (m & (kNearFace | kNearSolid))) pull_general<L, S>(a, x, y, z, c, raw);
+      if (m & (kNearFace | kNearSolid))
+        pull_fixup<L, S>(a, x, y, z, c, (m & kNearSolid) != 0, raw);
       stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
+      R chi = (R)0;
+      if (a.chi_max != (R)0)
+        chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
+      // (the moments are always returned in registers; a conditional
+      // pointer here would push them to scratch memory)
       CellMoments<R> mo;
-      const bool record = a.rec || a.recf;
-      if (m & kInSponge) {
-        const R chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
-        rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
-                                         cf, record ? &mo : nullptr);
-      } else {
-        rho = collide_coeffs<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref,
-                                          a.uref, cf, record ? &mo : nullptr);
-      }
-      if (record) {
+      rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
+                                       cf, &mo);
+      if (a.rec || a.recf) {
         // parent side: moments on the child box's boundary planes
         const int64_t r =
             a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
@@ -205,9 +213,17 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   });
 }
 
+// Wavefronts per SIMD the sweep is compiled for: 8 for the 4- and 2-byte
+// formats (the HBM stream needs them; without the hint the general path's
+// scalar registers alone would limit it to 7), no constraint for FP64.
+template <class S>
+struct SweepWaves {
+  static constexpr int value = sizeof(typename S::T) == 8 ? 1 : 8;
+};
+
 template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
-    k_sweep(const SweepArgs<S> a) {
+    __attribute__((amdgpu_waves_per_eu(SweepWaves<S>::value))) k_sweep(const SweepArgs<S> a) {
   // Tile b goes to workgroup b: the hardware deals workgroups round-robin
   // to the eight XCDs, so all XCDs stream through neighbouring tiles at the
   // same time (measured faster here than giving each XCD a contiguous eighth
@@ -370,7 +386,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_final(const double* part
 
 // Force on the SOLID cells by momentum exchange (Ladd; Mei et al. 2002):
 // for every link of a FLUID cell whose pulled source (under the face rules,
-// as in pull_general) is SOLID, the post-collision population f*_j moving
+// as in the sweep's pull) is SOLID, the post-collision population f*_j moving
 // into the wall (xi_j = -xi_i) returns reversed, so the wall receives
 // 2 f*_j xi_j.
 template <class L, class S>
@@ -545,27 +561,38 @@ __global__ void k_flags(FlagsArgs a) {
     if ((p[ax] == 0 && a.face[2 * ax] != kPeriodic) ||
         (p[ax] == dims[ax] - 1 && a.face[2 * ax + 1] != kPeriodic))
       flags |= kNearFace;
+  // sources mapped as the pull maps them: periodic wrap, or the face row
+  // for the other rules
   for (int i = 1; i < L::Q; ++i) {
     const Dir v = L::dir(i);
     int32_t s[3] = {p[0] - v.x, p[1] - v.y, p[2] - v.z};
-    bool inside = true;
     for (int ax = 0; ax < 3; ++ax) {
       if (s[ax] < 0 || s[ax] >= dims[ax]) {
         if (a.face[2 * ax] == kPeriodic)
           s[ax] = (s[ax] + dims[ax]) % dims[ax];
         else
-          inside = false;
+          s[ax] = s[ax] < 0 ? 0 : dims[ax] - 1;
       }
     }
-    if (inside &&
-        (a.mask[((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0]] & kKindBits) ==
-            kSolid)
+    if ((a.mask[((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0]] & kKindBits) ==
+        kSolid)
       flags |= kNearSolid;
   }
-  if (a.chi_max > 0.0 && sponge_chi<double>(a.sponge, a.chi_max, (uint32_t)p[0], (uint32_t)p[1],
-                                             (uint32_t)p[2], a.nx, a.ny, a.nz) > 0.0)
-    flags |= kInSponge;
   a.mask[c] = (uint8_t)((a.mask[c] & kKindBits) | flags);
+}
+
+// Tile summary: tiles[t] = 1 when the 64 cells [64 t, 64 t + 64) (those
+// that exist) are all FLUID without flags.
+__global__ void k_tiles(FlagsArgs a) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = a.nx * a.ny * a.nz;
+  const uint32_t c0 = t * 64u;
+  if (c0 >= n) return;
+  const uint32_t c1 = c0 + 64u < n ? c0 + 64u : n;
+  uint8_t plain = 1;
+  for (uint32_t c = c0; c < c1; ++c)
+    if (a.mask[c] != kFluid) plain = 0;
+  a.tiles[t] = plain;
 }
 
 // ------------------------------------------------------------------------
@@ -750,6 +777,7 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
   a.src = (const T*)h.src;
   a.dst = (T*)h.dst;
   a.mask = h.mask;
+  a.tiles = h.tiles;
   a.status = h.status;
   a.nx = h.nx;
   a.ny = h.ny;
@@ -928,6 +956,10 @@ hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st) {
     case 27: hipLaunchKernelGGL(k_flags<Lattice<27>>, dim3(blocks), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.tiles) return e;
+  const uint32_t ntile = (n + 63) / 64;
+  hipLaunchKernelGGL(k_tiles, dim3((ntile + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -29,11 +29,12 @@ enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
 // from fine data), RING (fine node rebuilt from coarse data); cells of the
 // three internal kinds are not swept.
 enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2, kCovered = 3, kImport = 4, kRing = 5 };
-// The mask byte holds the kind in its low three bits and flags computed at
-// initialisation: the cell lies in an absorbing layer (chi > 0), has a SOLID
-// neighbour, or lies on a non-periodic face.  Cells without the last two
-// pull like a periodic grid; cells without the first skip the sponge.
-enum : uint8_t { kKindBits = 0x07, kInSponge = 0x08, kNearFace = 0x40, kNearSolid = 0x80 };
+// The mask byte holds the kind in its low three bits and two flags computed
+// at initialisation: the cell has a SOLID neighbour, or it lies on a
+// non-periodic face.  Cells with neither flag pull like a periodic grid.
+// A tile of 64 consecutive cells (one wavefront) whose cells are all FLUID
+// without flags is "plain": its sweep does not read the mask at all.
+enum : uint8_t { kKindBits = 0x07, kNearFace = 0x40, kNearSolid = 0x80 };
 
 // ------------------------------------------------------------------------
 // Division of 32-bit unsigned numbers below 2^31 by a run-time invariant
@@ -147,6 +148,7 @@ struct SweepArgs {
   const T* src;          // post-collision state at t
   T* dst;                // post-collision state at t + 1
   const uint8_t* mask;   // nullptr = all fluid
+  const uint8_t* tiles;  // per 64-cell tile: 1 = plain (see the mask bits)
   int* status;           // sticky instability flag
   uint32_t nx, ny, nz, ncell;
   uint64_t pstride;      // population stride P >= ncell

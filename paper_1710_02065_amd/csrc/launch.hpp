@@ -16,6 +16,7 @@ struct SweepHost {
   const void* src;
   void* dst;
   const uint8_t* mask;  // nullptr = all fluid
+  const uint8_t* tiles;  // per 64-cell tile: 1 = every cell plain fluid
   int* status;
   uint32_t nx, ny, nz;
   uint64_t pstride;
@@ -47,14 +48,13 @@ struct RolesArgs {
   int32_t lo[3], hi[3];
 };
 
-// Flag bits of the mask (see kernels.hpp): in an absorbing layer, near a
-// SOLID cell, on a non-periodic face.
+// Flag bits of the mask (see kernels.hpp): near a SOLID cell, on a
+// non-periodic face; then the per-tile summary of the flagged mask.
 struct FlagsArgs {
   uint8_t* mask;
+  uint8_t* tiles;  // per 64-cell tile summary, filled after the flags
   uint32_t nx, ny, nz;
   int32_t face[6];
-  int32_t sponge[6];
-  double chi_max;
 };
 
 // Record box of the coarse moments filled from the initial fields.

@@ -155,7 +155,8 @@ static void level_layout(Level& L, int lattice, int storage) {
   L.off_buf[0] = 0;
   L.off_buf[1] = L.buf_bytes;
   L.off_mask = 2 * L.buf_bytes;
-  L.bytes = align_up(L.off_mask + (size_t)L.N, 256);
+  L.off_tiles = align_up(L.off_mask + (size_t)L.N, 256);
+  L.bytes = align_up(L.off_tiles + (size_t)(L.N + 63) / 64, 256);
 }
 
 void plan_layout(lbm_ctx* ctx) {
@@ -276,6 +277,7 @@ void assign_pointers(lbm_ctx* ctx) {
     L.buf[0] = b + L.off_buf[0];
     L.buf[1] = b + L.off_buf[1];
     L.mask = (uint8_t*)(b + L.off_mask);
+    L.tiles = (uint8_t*)(b + L.off_tiles);
   }
   assign_interface_pointers(ctx);
 }
@@ -313,6 +315,7 @@ SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
   h.src = L.buf[src_buf];
   h.dst = L.buf[src_buf ^ 1];
   h.mask = L.has_mask ? L.mask : nullptr;
+  h.tiles = L.has_mask ? L.tiles : nullptr;
   h.status = ctx->status;
   h.nx = (uint32_t)L.nx;
   h.ny = (uint32_t)L.ny;
@@ -494,11 +497,8 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
     fa.nx = (uint32_t)L.nx;
     fa.ny = (uint32_t)L.ny;
     fa.nz = (uint32_t)L.nz;
-    for (int f = 0; f < 6; ++f) {
-      fa.face[f] = L.face[f];
-      fa.sponge[f] = L.sponge[f];
-    }
-    fa.chi_max = L.chi_max;
+    for (int f = 0; f < 6; ++f) fa.face[f] = L.face[f];
+    fa.tiles = L.tiles;
     e = launch_flags(ctx->cfg.lattice, fa, ctx->stream);
     if (e != hipSuccess) return hip_error(e, "flags launch");
   }

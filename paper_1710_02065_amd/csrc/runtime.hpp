@@ -22,9 +22,10 @@ struct Level {
   int32_t sponge[6] = {0, 0, 0, 0, 0, 0};
   uint64_t pstride = 0;
   size_t buf_bytes = 0, bytes = 0, base_off = 0;
-  size_t off_buf[2] = {0, 0}, off_mask = 0;
+  size_t off_buf[2] = {0, 0}, off_mask = 0, off_tiles = 0;
   void* buf[2] = {nullptr, nullptr};
   uint8_t* mask = nullptr;
+  uint8_t* tiles = nullptr;  // per 64-cell tile: 1 = plain fluid (see k_tiles)
   bool has_mask = false;
   bool initialised = false;
   int cur = 0;    // buffer holding the current state

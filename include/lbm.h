@@ -259,9 +259,11 @@ int lbm_get_populations(lbm_ctx* ctx, int level, double* out);
 int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
 
 /* Serving: advance ctxs[k] by steps[k] coarse steps, k < n, sharing
- * launches between contexts.  All contexts must be unrefined, on one device
- * and one stream, and initialised.  Each context's result is bitwise the
- * same as lbm_step(ctxs[k], steps[k]) alone. */
+ * launches between contexts: the contexts are grouped by lattice, storage,
+ * sweep path (fully periodic or not) and workgroup size, and each group
+ * advances through one persistent launch per step.  All contexts must be
+ * unrefined, on one device and one stream, and initialised.  Each context's
+ * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */
 int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
 
 /* Time the sweep for each candidate workgroup size on this context's

@@ -500,7 +500,7 @@ __global__ void k_set_pop(PopArgs a) {
 // Each cell runs the same sweep_cell instantiation as a solo launch of its
 // context, so results are bitwise those of lbm_step.
 // ------------------------------------------------------------------------
-template <class L, class S>
+template <class L, class S, bool kGeneral>
 __device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_t c) {
   SweepArgs<S> a = to_args_dev<S>(J.h);
   const int p = (J.cur0 + s) & 1;
@@ -510,15 +510,14 @@ __device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_
   a.ncell = J.h.nx * J.h.ny * J.h.nz;
   a.div_nx = FastDiv{J.div_nx[0], J.div_nx[1], J.div_nx[2]};
   a.div_ny = FastDiv{J.div_ny[0], J.div_ny[1], J.div_ny[2]};
-  if (J.h.general)
-    sweep_cell<L, S, true>(a, c);
-  else
-    sweep_cell<L, S, false>(a, c);
+  sweep_cell<L, S, kGeneral>(a, c);
 }
 
-template <class L>
-__global__ void __launch_bounds__(1024) k_batch(const BatchJob* __restrict__ jobs,
-                                                const BatchHeader* __restrict__ hdr) {
+// One kernel per (lattice, storage, path): the contexts of a batch are
+// grouped so, which keeps each kernel as lean as the solo sweep.
+template <class L, class S, bool kGeneral>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SweepWaves<S>::value)))
+    k_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr) {
   const int32_t s = hdr->step;
   const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
   for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -532,12 +531,7 @@ __global__ void __launch_bounds__(1024) k_batch(const BatchJob* __restrict__ job
     if ((int64_t)s >= J.steps) continue;
     const uint32_t c = (tile - J.tile_begin) * blockDim.x + threadIdx.x;
     if (c >= J.h.nx * J.h.ny * J.h.nz) continue;
-    switch (J.storage) {
-      case 0: batch_cell<L, StoreF64>(J, s, c); break;
-      case 1: batch_cell<L, StoreF32>(J, s, c); break;
-      case 2: batch_cell<L, StoreF32S>(J, s, c); break;
-      case 3: batch_cell<L, StoreF16S>(J, s, c); break;
-    }
+    batch_cell<L, S, kGeneral>(J, s, c);
   }
 }
 
@@ -904,21 +898,52 @@ void fill_fastdiv(uint32_t d, uint32_t out[3]) {
   out[2] = f.s;
 }
 
-hipError_t launch_batch(int lattice, const BatchJob* jobs, BatchHeader* hdr, int block,
-                        int grid, hipStream_t st) {
-  switch (lattice) {
-    case 9: hipLaunchKernelGGL(k_batch<Lattice<9>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
-    case 19: hipLaunchKernelGGL(k_batch<Lattice<19>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
-    case 27: hipLaunchKernelGGL(k_batch<Lattice<27>>, dim3(grid), dim3(block), 0, st, jobs, hdr); break;
-    case kFullOrderCode + 9:
-      hipLaunchKernelGGL((k_batch<Lattice<9, true>>), dim3(grid), dim3(block), 0, st, jobs, hdr);
-      break;
-    case kFullOrderCode + 27:
-      hipLaunchKernelGGL((k_batch<Lattice<27, true>>), dim3(grid), dim3(block), 0, st, jobs, hdr);
-      break;
-    default: return hipErrorInvalidValue;
-  }
+// Batch kernel variants: variant = lattice code * 16 + storage * 2 + general.
+template <class L, class S, bool G>
+static hipError_t batch_t(bool query, const BatchJob* jobs, BatchHeader* hdr, int block,
+                          int grid, hipStream_t st, int* per) {
+  if (query)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_batch<L, S, G>, block, 0);
+  hipLaunchKernelGGL((k_batch<L, S, G>), dim3(grid), dim3(block), 0, st, jobs, hdr);
   return hipGetLastError();
+}
+
+template <class L>
+static hipError_t batch_l(int storage, bool general, bool query, const BatchJob* jobs,
+                          BatchHeader* hdr, int block, int grid, hipStream_t st, int* per) {
+#define HRLBM_BATCH(S)                                                            \
+  return general ? batch_t<L, S, true>(query, jobs, hdr, block, grid, st, per)    \
+                 : batch_t<L, S, false>(query, jobs, hdr, block, grid, st, per);
+  switch (storage) {
+    case 0: HRLBM_BATCH(StoreF64)
+    case 1: HRLBM_BATCH(StoreF32)
+    case 2: HRLBM_BATCH(StoreF32S)
+    case 3: HRLBM_BATCH(StoreF16S)
+  }
+#undef HRLBM_BATCH
+  return hipErrorInvalidValue;
+}
+
+static hipError_t batch_dispatch(int variant, bool query, const BatchJob* jobs,
+                                 BatchHeader* hdr, int block, int grid, hipStream_t st,
+                                 int* per) {
+  const int lattice = variant / 16, storage = (variant / 2) % 8;
+  const bool general = variant & 1;
+  switch (lattice) {
+    case 9: return batch_l<Lattice<9>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case 19: return batch_l<Lattice<19>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case 27: return batch_l<Lattice<27>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case kFullOrderCode + 9:
+      return batch_l<Lattice<9, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case kFullOrderCode + 27:
+      return batch_l<Lattice<27, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int block,
+                        int grid, hipStream_t st) {
+  return batch_dispatch(variant, false, jobs, hdr, block, grid, st, nullptr);
 }
 
 hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st) {
@@ -926,24 +951,14 @@ hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st) {
   return hipGetLastError();
 }
 
-int batch_grid(int lattice, int block) {
+int batch_grid(int variant, int block) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  hipError_t e = hipErrorInvalidValue;
-  switch (lattice) {
-    case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<9>>, block, 0); break;
-    case 19: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<19>>, block, 0); break;
-    case 27: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<27>>, block, 0); break;
-    case kFullOrderCode + 9:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<9, true>>, block, 0);
-      break;
-    case kFullOrderCode + 27:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<Lattice<27, true>>, block, 0);
-      break;
-  }
-  if (e != hipSuccess || per < 1) per = 1;
+  if (batch_dispatch(variant, true, nullptr, nullptr, block, 0, nullptr, &per) != hipSuccess ||
+      per < 1)
+    per = 1;
   return cus * per;
 }
 

@@ -196,10 +196,11 @@ struct BatchHeader {
 hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
                         hipStream_t st);
 // persistent batched sweep: grid of `grid` workgroups of `block` threads
-hipError_t launch_batch(int lattice, const BatchJob* jobs, BatchHeader* hdr, int block,
+// variant = lattice code * 16 + storage * 2 + (general path ? 1 : 0)
+hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int block,
                         int grid, hipStream_t st);
 hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st);
-int batch_grid(int lattice, int block);  // resident workgroups on the device
+int batch_grid(int variant, int block);  // resident workgroups on the device
 void fill_fastdiv(uint32_t d, uint32_t out[3]);
 hipError_t launch_init(int lattice, int storage, const InitArgs& a, uint32_t n,
                        hipStream_t st);

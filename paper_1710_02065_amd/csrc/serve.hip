@@ -33,7 +33,7 @@ struct BatchRunner {
   BatchHeader* h_hdr = nullptr;
   hipEvent_t staged = nullptr;  // the last upload finished reading staging
   hipStream_t capture = nullptr;
-  std::map<std::pair<int, int>, GraphEntry> graphs;  // (lattice, block)
+  std::map<std::pair<int, int>, GraphEntry> graphs;  // (kernel variant, block)
   std::map<std::pair<int, int>, int> grids;
 };
 
@@ -91,15 +91,15 @@ static int ensure_capacity(BatchRunner* r, size_t n) {
   return LBM_OK;
 }
 
-static int graph_for(BatchRunner* r, int lattice, int block, int grid, GraphEntry** out) {
-  auto key = std::make_pair(lattice, block);
+static int graph_for(BatchRunner* r, int variant, int block, int grid, GraphEntry** out) {
+  auto key = std::make_pair(variant, block);
   auto it = r->graphs.find(key);
   if (it == r->graphs.end()) {
     GraphEntry g{};
     hipError_t e = hipStreamBeginCapture(r->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "batch capture begin");
     for (int k = 0; k < kBatchGraphSteps && e == hipSuccess; ++k) {
-      e = launch_batch(lattice, r->d_jobs, r->d_hdr, block, grid, r->capture);
+      e = launch_batch(variant, r->d_jobs, r->d_hdr, block, grid, r->capture);
       if (e == hipSuccess) e = launch_batch_bump(r->d_hdr, r->capture);
     }
     hipGraph_t graph = nullptr;
@@ -118,10 +118,16 @@ static int graph_for(BatchRunner* r, int lattice, int block, int grid, GraphEntr
   return LBM_OK;
 }
 
-// One batch of contexts sharing a lattice.
+// Batch kernel variant of a context: lattice code, storage, sweep path.
+static int batch_variant(const lbm_ctx* c) {
+  const SweepHost h = sweep_args(c, 0, 0, 0);
+  return kernel_lattice(c->cfg) * 16 + c->cfg.storage * 2 + (h.general ? 1 : 0);
+}
+
+// One batch of contexts sharing a kernel variant and workgroup size.
 static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64_t>>& grp) {
   lbm_ctx* c0 = grp[0].first;
-  const int lattice = kernel_lattice(c0->cfg);
+  const int variant = batch_variant(c0);
   const int block = c0->block;
   int rc = ensure_capacity(r, grp.size());
   if (rc != LBM_OK) return rc;
@@ -159,15 +165,15 @@ static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64
                        r->stream);
   if (e == hipSuccess) e = hipEventRecord(r->staged, r->stream);
   if (e != hipSuccess) return hip_error(e, "batch table upload");
-  auto gk = std::make_pair(lattice, block);
-  if (!r->grids.count(gk)) r->grids[gk] = batch_grid(lattice, block);
+  auto gk = std::make_pair(variant, block);
+  if (!r->grids.count(gk)) r->grids[gk] = batch_grid(variant, block);
   const int grid = r->grids[gk];
   if (grid <= 0) return set_error(LBM_EDEVICE, "batch occupancy query failed");
   int64_t done = 0;
   const bool use_graph = !(c0->cfg.flags & LBM_NO_GRAPH);
   if (use_graph && max_steps >= kBatchGraphSteps) {
     GraphEntry* g = nullptr;
-    rc = graph_for(r, lattice, block, grid, &g);
+    rc = graph_for(r, variant, block, grid, &g);
     if (rc != LBM_OK) return rc;
     for (; done + kBatchGraphSteps <= max_steps; done += kBatchGraphSteps) {
       e = hipGraphLaunch(g->exec, r->stream);
@@ -175,7 +181,7 @@ static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64
     }
   }
   for (; done < max_steps; ++done) {
-    e = launch_batch(lattice, r->d_jobs, r->d_hdr, block, grid, r->stream);
+    e = launch_batch(variant, r->d_jobs, r->d_hdr, block, grid, r->stream);
     if (e == hipSuccess) e = launch_batch_bump(r->d_hdr, r->stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
@@ -297,10 +303,10 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
   BatchRunner* r = nullptr;
   rc = runner_for(ctxs[0]->device, ctxs[0]->stream, &r);
   if (rc != LBM_OK) return rc;
-  // one persistent launch sequence per (lattice, workgroup size)
+  // one persistent launch sequence per (kernel variant, workgroup size)
   std::map<std::pair<int, int>, std::vector<std::pair<lbm_ctx*, int64_t>>> groups;
   for (int k = 0; k < n; ++k)
-    groups[std::make_pair(kernel_lattice(ctxs[k]->cfg), ctxs[k]->block)].push_back(
+    groups[std::make_pair(batch_variant(ctxs[k]), ctxs[k]->block)].push_back(
         {ctxs[k], steps[k]});
   for (auto& kv : groups) {
     rc = run_group(r, kv.second);

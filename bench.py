@@ -243,7 +243,10 @@ def other_configs(lbm, torch, steps, shedding_steps):
         from paper_1710_02065_amd import cylinder_study
         w = min(60000, shedding_steps // 2)
         res["d2q9_cylinder_2048x1024_shedding"] = cylinder_study.run(
-            steps=shedding_steps, window=w, acoustics=False, log=log)
+            steps=shedding_steps, window=w, acoustics=False,
+            probe_cells=W.cylinder_probes(nx, ny, D, 400, 512), log=log)
+        res["d2q9_cylinder_2048x1024_shedding"]["probes"] = (
+            "p = cs^2 rho every 10 steps at r = 1.5, 2, 3, 4 D along 90 and 78.2 degrees")
         torch.cuda.empty_cache()
     # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
     # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]

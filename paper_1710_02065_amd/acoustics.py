@@ -70,6 +70,18 @@ def amplitude(x):
     return 0.5 * float(x.max() - x.min())
 
 
+def tone_amplitude(x, f, dt=1.0):
+    """Amplitude of the component of x at frequency f: least-squares fit of
+    c0 + a cos(2 pi f t) + b sin(2 pi f t), returns sqrt(a^2 + b^2).  It
+    separates a shedding tone from slow drifts and other frequencies."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.arange(len(x)) * dt
+    w = 2.0 * math.pi * f
+    M = np.stack([np.ones_like(t), np.cos(w * t), np.sin(w * t)], axis=1)
+    c = np.linalg.lstsq(M, x, rcond=None)[0]
+    return float(math.hypot(c[1], c[2]))
+
+
 def fluctuation(p, axis=0):
     """Fluctuating pressure: p minus its temporal mean along `axis`."""
     p = np.asarray(p, dtype=np.float64)

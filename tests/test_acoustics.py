@@ -87,3 +87,11 @@ def test_directivity_peak_and_ring():
     assert A.directivity_peak(rms, ang) == pytest.approx(78.2, abs=0.1)
     cells = A.ring_cells(64, 32, 20, 16, 10, [0.0, 90.0, 180.0])
     assert cells.tolist() == [16 * 64 + 30, 26 * 64 + 20, 16 * 64 + 10]
+
+
+def test_tone_amplitude_rejects_drift_and_other_tones():
+    n = 20000
+    t = np.arange(n)
+    x = (0.7 * np.sin(2 * math.pi * t / 431.0 + 1.1) + 2e-5 * t
+         + 0.3 * np.sin(2 * math.pi * t / 97.0))
+    assert A.tone_amplitude(x, 1 / 431.0) == pytest.approx(0.7, rel=2e-3)

@@ -508,6 +508,13 @@ typedef struct {
   double inlet_noise;
   int full_order;           /* 1: full recursive regularization */
   int levels;               /* levels of the hierarchy this grid belongs to */
+  /* absorbing layer given per cell (Sec. II.C with an arbitrary geometry,
+   * e.g. circular, and spatially varying reference fields): when sp_chi is
+   * set it replaces the face profile; sp_rho [N] and sp_u [3][N] (each may be
+   * NULL: rho_ref, u_ref) give the reference state per cell */
+  const double* sp_chi;
+  const double* sp_rho;
+  const double* sp_u;
 } ora_grid;
 
 /* Sponge strength chi(x) = chi_max * max over faces of the polynomial
@@ -516,6 +523,14 @@ typedef struct {
  * with s the coordinate normal to the face, s0 = n - W the inner edge and
  * L = n one past the last node, for a face of width W on an axis of n nodes;
  * the low face uses the mirrored coordinate n - 1 - x. */
+/* The profile itself, for a coordinate s across a layer from its inner
+ * edge s0 to L (zero outside [s0, L]); used for other layer geometries
+ * (e.g. circular, with s the distance from a centre). */
+double ora_sponge_sigma(double s, double s0, double L) {
+  if (s < s0 || s > L) return 0.0;
+  return 3125.0 * (L - s) * pow(s - s0, 4) / (256.0 * pow(L - s0, 5));
+}
+
 double ora_sponge_chi(const ora_grid* g, int64_t x, int64_t y, int64_t z) {
   int64_t pos[3] = {x, y, z}, dims[3] = {g->nx, g->ny, g->nz};
   double best = 0.0;
@@ -677,13 +692,16 @@ void ora_step_ex(const ora_grid* g, const uint8_t* mask, const uint8_t* skip,
           if (L.d == 2) uin[2] = 0.0;
           ora_feq(&L, g->rho0, uin, post);
         } else {
-          double chi = ora_sponge_chi(g, x, y, z);
+          double chi = g->sp_chi ? g->sp_chi[c] : ora_sponge_chi(g, x, y, z);
+          double rref = g->sp_rho ? g->sp_rho[c] : g->rho_ref, uref[3];
           double rs, us[3], a2p[6];
           int a;
+          for (a = 0; a < 3; ++a)
+            uref[a] = g->sp_u ? g->sp_u[(int64_t)a * N + c] : g->u_ref[a];
+          if (L.d == 2) uref[2] = 0.0;
           for (i = 0; i < L.q; ++i)
             f[i] = ora_pull(g, &L, mask, fin, x, y, z, i);
-          ora_collide_cell(&L, f, g->tau, chi, g->rho_ref, g->u_ref, post,
-                           &rs, us, a2p);
+          ora_collide_cell(&L, f, g->tau, chi, rref, uref, post, &rs, us, a2p);
           if (rho_out) rho_out[c] = rs;
           if (u_out)
             for (a = 0; a < 3; ++a) u_out[(int64_t)a * N + c] = us[a];

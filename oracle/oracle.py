@@ -39,6 +39,8 @@ def lib():
         L.ora_splitmix64.restype = C.c_uint64
         L.ora_sponge_chi.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64]
         L.ora_sponge_chi.restype = C.c_double
+        L.ora_sponge_sigma.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.ora_sponge_sigma.restype = C.c_double
         L.ora_init.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.ora_step.argtypes = [C.c_void_p, C.c_void_p, dp, dp, C.c_int64]
         L.ora_moments.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp]
@@ -78,6 +80,7 @@ class OraGrid(C.Structure):
         ("chi_max", C.c_double), ("rho_ref", C.c_double), ("u_ref", C.c_double * 3),
         ("seed", C.c_uint64), ("inlet_noise", C.c_double), ("full_order", C.c_int),
         ("levels", C.c_int),
+        ("sp_chi", C.c_void_p), ("sp_rho", C.c_void_p), ("sp_u", C.c_void_p),
     ]
 
 
@@ -146,6 +149,22 @@ def collide_bgk(q, f, tau, chi=0.0, rho_ref=1.0, u_ref=(0.0, 0.0, 0.0)):
     return out
 
 
+def sponge_sigma(s, s0, L):
+    """Absorbing-layer profile of Sec. II.C at coordinate s across a layer
+    from s0 to L (0 outside)."""
+    return lib().ora_sponge_sigma(float(s), float(s0), float(L))
+
+
+def circular_sponge(shape, center, r0, r1, chi_max):
+    """chi per cell for a circular (2D) or spherical layer: the profile in
+    the distance from `center`, from r0 to r1 (test input builder)."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2 +
+                (0.0 if nz == 1 else (z - center[2]) ** 2)).ravel()
+    return np.array([chi_max * sponge_sigma(v, r0, r1) for v in r])
+
+
 def splitmix64(seed, k):
     return int(lib().ora_splitmix64(C.c_uint64(seed), C.c_uint64(k)))
 
@@ -182,6 +201,7 @@ class Grid:
         g.full_order = 1 if full_order else 0
         g.levels = levels
         self.g = g
+        self._sponge = None
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
         if self.mask is not None:
             assert self.mask.size == self.N
@@ -221,6 +241,20 @@ class Grid:
         u = np.empty((3, self.N))
         lib().ora_moments(C.byref(self.g), self._mask_ptr, _dp(self.f), _dp(rho), _dp(u))
         return rho, u
+
+    def set_sponge(self, chi, rho_ref=None, u_ref=None):
+        """Absorbing layer given per cell: chi [N] (replaces the face
+        profile), reference density [N] and velocity [3][N] (None: the
+        constant references)."""
+        N = self.N
+        arrs = [np.ascontiguousarray(chi, dtype=np.float64).reshape(N),
+                None if rho_ref is None else np.ascontiguousarray(rho_ref, dtype=np.float64).reshape(N),
+                None if u_ref is None else np.ascontiguousarray(u_ref, dtype=np.float64).reshape(3, N)]
+        self._sponge = arrs  # kept alive while the grid points at them
+        self.g.sp_chi = arrs[0].ctypes.data
+        self.g.sp_rho = None if arrs[1] is None else arrs[1].ctypes.data
+        self.g.sp_u = None if arrs[2] is None else arrs[2].ctypes.data
+        return self
 
     def chi(self, x, y, z=0):
         return lib().ora_sponge_chi(C.byref(self.g), x, y, z)

@@ -99,6 +99,8 @@ enum {
 #define LBM_ALLOW_HIGH_MA 0x1u /* accept Ma > 0.6 (beyond the stable range
                                   reported in the paper's conclusions) */
 #define LBM_NO_GRAPH 0x2u      /* never replay step sequences as hipGraphs */
+#define LBM_SPONGE_FIELD 0x8u  /* reserve per-cell absorbing-layer storage
+                                  (lbm_set_sponge) on every level */
 #define LBM_FULL_ORDER 0x4u    /* full recursive regularization (Sec. II.A,
                                   order n > 2): every Hermite polynomial the
                                   lattice resolves, up to fourth order on
@@ -129,7 +131,8 @@ typedef struct lbm_config {
   uint64_t seed;         /* inlet noise seed */
   double inlet_noise;    /* relative inlet velocity noise amplitude */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
-  uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER */
+  uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER |
+                            LBM_SPONGE_FIELD */
   uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
   int32_t nest_count;    /* further nested boxes, 0 .. LBM_MAX_LEVELS - 2
                             (needs refine_lo/hi) */
@@ -215,6 +218,21 @@ int lbm_moments(lbm_ctx* ctx, int level, double* rho_out, double* u_out);
  * pointer of cell indices, rho_out [n] FP64 device pointer. */
 int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n,
               double* rho_out);
+
+/* Absorbing layer given per cell (Sec. II.C with any geometry, e.g. the
+ * circular layer of the paper's cylinder setup, and spatially varying
+ * reference fields such as a jet similarity profile): chi [N], rho_ref [N]
+ * and u_ref [3][N] are FP64 device pointers over the level's cells (rho_ref
+ * and u_ref may be NULL: the constant references of the configuration).
+ * Cells with chi > 0 relax towards their own reference exactly as in the
+ * face layers (eqs. spongeLB, dampingLBM, modifiedMoments); on this level
+ * the face profile (sponge_width, chi_max) is no longer applied.  The
+ * values are copied.  Needs LBM_SPONGE_FIELD at create; call after
+ * lbm_init of the level (lbm_init clears it).  Rejects chi < 0,
+ * chi >= 4 tau of the level (Sec. II.C) and non-finite values (synchronous
+ * check on the host). */
+int lbm_set_sponge(lbm_ctx* ctx, int level, const double* chi, const double* rho_ref,
+                   const double* u_ref);
 
 /* Running field statistics for the fluctuating pressure of Sec. III (the
  * pressure minus its temporal mean, p = cs^2 rho): adds x = rho - rho0 of

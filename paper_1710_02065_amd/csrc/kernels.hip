@@ -174,14 +174,19 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       if (m & (kNearFace | kNearSolid))
         pull_fixup<L, S>(a, x, y, z, c, (m & kNearSolid) != 0, raw);
       stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
-      R chi = (R)0;
-      if (a.chi_max != (R)0)
+      R chi = (R)0, rref = a.rho_ref, uref[3] = {a.uref[0], a.uref[1], a.uref[2]};
+      if (m & kFieldSponge) {
+        chi = a.sp[c];
+        rref = a.sp[a.ncell + c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) uref[k] = a.sp[(uint64_t)(2 + k) * a.ncell + c];
+      } else if (a.chi_max != (R)0) {
         chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
+      }
       // (the moments are always returned in registers; a conditional
       // pointer here would push them to scratch memory)
       CellMoments<R> mo;
-      rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, a.rho_ref, a.uref,
-                                       cf, &mo);
+      rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, rref, uref, cf, &mo);
       if (a.rec || a.recf) {
         // parent side: moments on the child box's boundary planes
         const int64_t r =
@@ -215,15 +220,19 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
 
 // Wavefronts per SIMD the sweep is compiled for: 8 for the 4- and 2-byte
 // formats (the HBM stream needs them; without the hint the general path's
-// scalar registers alone would limit it to 7), no constraint for FP64.
-template <class S>
+// scalar registers alone would limit it to 7), except the D3Q27 general
+// path, whose 27 pulled values need more than the 64 registers 8 waves
+// leave (7 waves, no spills); no constraint for FP64.
+template <class L, class S, bool kGeneral>
 struct SweepWaves {
-  static constexpr int value = sizeof(typename S::T) == 8 ? 1 : 8;
+  static constexpr int value =
+      sizeof(typename S::T) == 8 ? 1 : (L::Q == 27 && kGeneral ? 7 : 8);
 };
 
 template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
-    __attribute__((amdgpu_waves_per_eu(SweepWaves<S>::value))) k_sweep(const SweepArgs<S> a) {
+    __attribute__((amdgpu_waves_per_eu(SweepWaves<L, S, kGeneral>::value)))
+    k_sweep(const SweepArgs<S> a) {
   // Tile b goes to workgroup b: the hardware deals workgroups round-robin
   // to the eight XCDs, so all XCDs stream through neighbouring tiles at the
   // same time (measured faster here than giving each XCD a contiguous eighth
@@ -516,7 +525,8 @@ __device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_
 // One kernel per (lattice, storage, path): the contexts of a batch are
 // grouped so, which keeps each kernel as lean as the solo sweep.
 template <class L, class S, bool kGeneral>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SweepWaves<S>::value)))
+__global__ void __launch_bounds__(1024)
+    __attribute__((amdgpu_waves_per_eu(SweepWaves<L, S, kGeneral>::value)))
     k_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr) {
   const int32_t s = hdr->step;
   const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
@@ -573,6 +583,32 @@ __global__ void k_flags(FlagsArgs a) {
       flags |= kNearSolid;
   }
   a.mask[c] = (uint8_t)((a.mask[c] & kKindBits) | flags);
+}
+
+// Absorbing layer given per cell: convert to the compute type and flag the
+// cells with chi > 0 (the flag is cleared elsewhere).
+template <class R>
+__global__ void k_set_sponge(SpongeArgs a) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  R* sp = (R*)a.sp;
+  const double chi = a.chi[c];
+  sp[c] = (R)chi;
+  sp[a.n + c] = (R)(a.rho_ref ? a.rho_ref[c] : a.rho_ref0);
+  for (int k = 0; k < 3; ++k)
+    sp[(uint64_t)(2 + k) * a.n + c] =
+        (R)(a.u_ref ? a.u_ref[(uint64_t)k * a.n + c] : a.u_ref0[k]);
+  const uint8_t m = a.mask[c];
+  a.mask[c] = chi > 0.0 ? (uint8_t)(m | kFieldSponge) : (uint8_t)(m & ~kFieldSponge);
+}
+
+hipError_t launch_set_sponge(int storage, const SpongeArgs& a, hipStream_t st) {
+  const uint32_t blocks = (a.n + 255) / 256;
+  if (storage == 0)
+    hipLaunchKernelGGL(k_set_sponge<double>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_set_sponge<float>, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // Tile summary: tiles[t] = 1 when the 64 cells [64 t, 64 t + 64) (those
@@ -802,6 +838,7 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
   a.ntiles = 0;
   a.rec = (R*)h.rec;
   a.recf = (R*)h.recf;
+  a.sp = (const R*)h.sp;
   for (int k = 0; k < 3; ++k) {
     a.rec_off[k] = h.rec_off[k];
     a.rec_dim[k] = h.rec_dim[k];
@@ -973,6 +1010,11 @@ hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.tiles) return e;
+  return launch_tiles(a, st);
+}
+
+hipError_t launch_tiles(const FlagsArgs& a, hipStream_t st) {
+  const uint32_t n = a.nx * a.ny * a.nz;
   const uint32_t ntile = (n + 63) / 64;
   hipLaunchKernelGGL(k_tiles, dim3((ntile + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();

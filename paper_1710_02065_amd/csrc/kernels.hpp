@@ -29,12 +29,13 @@ enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
 // from fine data), RING (fine node rebuilt from coarse data); cells of the
 // three internal kinds are not swept.
 enum : uint8_t { kFluid = 0, kSolid = 1, kInlet = 2, kCovered = 3, kImport = 4, kRing = 5 };
-// The mask byte holds the kind in its low three bits and two flags computed
-// at initialisation: the cell has a SOLID neighbour, or it lies on a
-// non-periodic face.  Cells with neither flag pull like a periodic grid.
+// The mask byte holds the kind in its low three bits and flags: the cell
+// has a SOLID neighbour, or it lies on a non-periodic face (both computed at
+// initialisation; cells with neither pull like a periodic grid), or it lies
+// in an absorbing layer given per cell.
 // A tile of 64 consecutive cells (one wavefront) whose cells are all FLUID
 // without flags is "plain": its sweep does not read the mask at all.
-enum : uint8_t { kKindBits = 0x07, kNearFace = 0x40, kNearSolid = 0x80 };
+enum : uint8_t { kKindBits = 0x07, kFieldSponge = 0x08, kNearFace = 0x40, kNearSolid = 0x80 };
 
 // ------------------------------------------------------------------------
 // Division of 32-bit unsigned numbers below 2^31 by a run-time invariant
@@ -176,6 +177,9 @@ struct SweepArgs {
   // the parent's IMPORT nodes filter are recorded into recf (10 components,
   // SoA over all ncell nodes of this level); nullptr disables it
   R* recf;
+  // absorbing layer given per cell: chi, rho_ref, u_ref (5 x ncell), read
+  // for cells flagged kFieldSponge; nullptr: none
+  const R* sp;
 };
 
 // Band of a child level whose pre-collision moments its parent's IMPORT

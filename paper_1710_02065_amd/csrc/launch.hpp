@@ -36,6 +36,21 @@ struct SweepHost {
   int32_t box_lo[3], box_hi[3];
   // child-side record of the import band (nullptr: off)
   void* recf;
+  // absorbing layer given per cell (5 x N values of the compute type)
+  const void* sp;
+};
+
+// Absorbing layer given per cell: FP64 inputs converted into `sp`
+// (chi, rho_ref, u_ref x 3, each over N cells) and the kFieldSponge flag set
+// in the mask where chi > 0.
+struct SpongeArgs {
+  const double* chi;
+  const double* rho_ref;
+  const double* u_ref;
+  double rho_ref0, u_ref0[3];
+  void* sp;
+  uint8_t* mask;
+  uint32_t n;
 };
 
 // Mark the refinement roles in a level's mask: with a parent, RING on the
@@ -208,6 +223,8 @@ hipError_t launch_moments(int lattice, int storage, const MomentArgs& a,
                           uint32_t n, hipStream_t st);
 hipError_t launch_accum(int lattice, int storage, const AccumArgs& a, uint32_t n,
                         hipStream_t st);
+hipError_t launch_set_sponge(int storage, const SpongeArgs& a, hipStream_t st);
+hipError_t launch_tiles(const FlagsArgs& a, hipStream_t st);
 hipError_t launch_force(int lattice, int storage, const ReduceArgs& a, hipStream_t st);
 hipError_t launch_totals(int lattice, int storage, const ReduceArgs& a, hipStream_t st);
 hipError_t launch_probe(int lattice, int storage, const ProbeArgs& a,

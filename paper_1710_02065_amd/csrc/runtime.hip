@@ -146,7 +146,7 @@ int validate(const lbm_config* cfg) {
 }
 
 // device memory layout of one level: A, B, mask
-static void level_layout(Level& L, int lattice, int storage) {
+static void level_layout(Level& L, int lattice, int storage, bool sponge_field) {
   const int q = lattice;
   L.q = q;
   L.pstride = pop_stride((uint64_t)L.N);
@@ -156,7 +156,9 @@ static void level_layout(Level& L, int lattice, int storage) {
   L.off_buf[1] = L.buf_bytes;
   L.off_mask = 2 * L.buf_bytes;
   L.off_tiles = align_up(L.off_mask + (size_t)L.N, 256);
-  L.bytes = align_up(L.off_tiles + (size_t)(L.N + 63) / 64, 256);
+  L.off_sponge = align_up(L.off_tiles + (size_t)(L.N + 63) / 64, 256);
+  const size_t rsz = storage == LBM_F64 ? 8 : 4;
+  L.bytes = align_up(L.off_sponge + (sponge_field ? 5 * (size_t)L.N * rsz : 0), 256);
 }
 
 void plan_layout(lbm_ctx* ctx) {
@@ -165,7 +167,7 @@ void plan_layout(lbm_ctx* ctx) {
   size_t off = 256 + align_up(sizeof(double) * kRedMax * kRedBlocks, 256);
   for (int l = 0; l < ctx->nlevels; ++l) {
     Level& L = ctx->lv[l];
-    level_layout(L, c.lattice, c.storage);
+    level_layout(L, c.lattice, c.storage, (c.flags & LBM_SPONGE_FIELD) != 0);
     L.base_off = off;
     off += L.bytes;
   }
@@ -278,6 +280,7 @@ void assign_pointers(lbm_ctx* ctx) {
     L.buf[1] = b + L.off_buf[1];
     L.mask = (uint8_t*)(b + L.off_mask);
     L.tiles = (uint8_t*)(b + L.off_tiles);
+    L.sp = (ctx->cfg.flags & LBM_SPONGE_FIELD) ? (void*)(b + L.off_sponge) : nullptr;
   }
   assign_interface_pointers(ctx);
 }
@@ -330,6 +333,11 @@ SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
     h.uin[a] = ctx->uin[a];
   }
   h.noise = c.inlet_noise;
+  if (L.field_sponge) {
+    // the per-cell layer replaces the face profile on this level
+    h.sp = L.sp;
+    h.chi_max = 0.0;
+  }
   bool general = L.has_mask || L.chi_max > 0;
   for (int f = 0; f < 6; ++f) {
     h.face[f] = L.face[f];
@@ -483,7 +491,8 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   if (e != hipSuccess) return hip_error(e, "init launch");
   // any level that is not a fully periodic, sponge-free, unrefined grid
   // keeps a mask (all FLUID if none was given) with the flag bits
-  bool general = mask != nullptr || ctx->nlevels > 1 || L.chi_max > 0;
+  bool general = mask != nullptr || ctx->nlevels > 1 || L.chi_max > 0 ||
+                 (ctx->cfg.flags & LBM_SPONGE_FIELD);
   for (int f = 0; f < 6; ++f)
     if (L.face[f] != LBM_PERIODIC) general = true;
   L.has_mask = general;
@@ -518,6 +527,7 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   }
   L.cur = 0;
   L.t = 0;
+  L.field_sponge = false;
   L.initialised = true;
   if (ctx->cfg.block == 0) {
     const int tb = tuned_block(ctx);
@@ -642,6 +652,51 @@ int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2) {
   a.rho0 = ctx->cfg.rho0;
   hipError_t e = launch_accum(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "accumulate launch");
+  return LBM_OK;
+}
+
+int lbm_set_sponge(lbm_ctx* ctx, int level, const double* chi, const double* rho_ref,
+                   const double* u_ref) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level >= ctx->nlevels || !chi)
+    return set_error(LBM_EINVAL, "level %d / chi", level);
+  if (!(ctx->cfg.flags & LBM_SPONGE_FIELD))
+    return set_error(LBM_ESTATE, "create the context with LBM_SPONGE_FIELD");
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  Level& L = ctx->lv[level];
+  // Sec. II.C: 0 <= chi < 4 tau of the level (checked on a host copy)
+  std::vector<double> hc((size_t)L.N);
+  hipError_t e = hipMemcpyAsync(hc.data(), chi, (size_t)L.N * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "sponge copy");
+  for (double v : hc)
+    if (!(v >= 0.0) || !(v < 4.0 * L.tau))
+      return set_error(LBM_EINVAL, "sponge chi = %g outside [0, 4 tau = %g)", v, 4.0 * L.tau);
+  SpongeArgs a{};
+  a.chi = chi;
+  a.rho_ref = rho_ref;
+  a.u_ref = u_ref;
+  a.rho_ref0 = ctx->cfg.rho_ref;
+  for (int k = 0; k < 3; ++k)
+    a.u_ref0[k] = ctx->cfg.lattice == LBM_D2Q9 && k == 2 ? 0.0 : ctx->cfg.u_ref[k];
+  a.sp = L.sp;
+  a.mask = L.mask;
+  a.n = (uint32_t)L.N;
+  e = launch_set_sponge(ctx->cfg.storage, a, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "sponge launch");
+  FlagsArgs fa{};
+  fa.mask = L.mask;
+  fa.tiles = L.tiles;
+  fa.nx = (uint32_t)L.nx;
+  fa.ny = (uint32_t)L.ny;
+  fa.nz = (uint32_t)L.nz;
+  e = launch_tiles(fa, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "tiles launch");
+  L.field_sponge = true;
+  drop_graphs(ctx);
   return LBM_OK;
 }
 

@@ -22,10 +22,12 @@ struct Level {
   int32_t sponge[6] = {0, 0, 0, 0, 0, 0};
   uint64_t pstride = 0;
   size_t buf_bytes = 0, bytes = 0, base_off = 0;
-  size_t off_buf[2] = {0, 0}, off_mask = 0, off_tiles = 0;
+  size_t off_buf[2] = {0, 0}, off_mask = 0, off_tiles = 0, off_sponge = 0;
   void* buf[2] = {nullptr, nullptr};
   uint8_t* mask = nullptr;
   uint8_t* tiles = nullptr;  // per 64-cell tile: 1 = plain fluid (see k_tiles)
+  void* sp = nullptr;        // per-cell absorbing layer (LBM_SPONGE_FIELD)
+  bool field_sponge = false; // set by lbm_set_sponge since the last init
   bool has_mask = false;
   bool initialised = false;
   int cur = 0;    // buffer holding the current state

@@ -21,7 +21,7 @@ LBM_PERIODIC, LBM_FREESLIP, LBM_OUTFLOW = 0, 1, 2
 LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER = 0x1, 0x2, 0x4
+LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER, LBM_SPONGE_FIELD = 0x1, 0x2, 0x4, 0x8
 LBM_MAX_LEVELS = 5
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S}
@@ -31,7 +31,7 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
-           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_get_populations", "lbm_set_populations",
+           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_set_sponge", "lbm_get_populations", "lbm_set_populations",
            "lbm_step_batch", "lbm_autotune", "lbm_destroy", "lbm_lattice_table",
            "lbm_last_error"]
 
@@ -90,6 +90,7 @@ def lib():
         L.lbm_probe.argtypes = [vp, C.c_int, vp, C.c_int, dp]
         L.lbm_force.argtypes = [vp, C.c_int, dp]
         L.lbm_totals.argtypes = [vp, C.c_int, dp]
+        L.lbm_set_sponge.argtypes = [vp, C.c_int, dp, dp, dp]
         L.lbm_accumulate.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_get_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
@@ -176,6 +177,10 @@ def lbm_accumulate(ctx, level, sum1, sum2):
 
 def lbm_force(ctx, level, out):
     return _check(lib().lbm_force(ctx, level, _ptr(out)))
+
+
+def lbm_set_sponge(ctx, level, chi, rho_ref=None, u_ref=None):
+    return _check(lib().lbm_set_sponge(ctx, level, _ptr(chi), _ptr(rho_ref), _ptr(u_ref)))
 
 
 def lbm_totals(ctx, level, out):
@@ -341,6 +346,22 @@ class Simulation:
             out = self.torch.empty(3, dtype=self.torch.float64, device=self.device)
         lbm_force(self.ctx, level, out)
         return out
+
+    def set_sponge(self, chi, rho_ref=None, u_ref=None, level=0):
+        """Absorbing layer given per cell (needs LBM_SPONGE_FIELD): chi [N],
+        rho_ref [N], u_ref [3][N]; host or device arrays."""
+        t = self.torch
+        chi = self._dev(chi, t.float64)
+        rho_ref = self._dev(rho_ref, t.float64)
+        u_ref = self._dev(u_ref, t.float64)
+        if u_ref is not None:
+            u_ref = u_ref.reshape(-1, self.ncell(level))
+            if u_ref.shape[0] < 3:
+                u_ref = t.cat([u_ref, t.zeros(3 - u_ref.shape[0], u_ref.shape[1],
+                                              dtype=t.float64, device=self.device)])
+            u_ref = u_ref.contiguous()
+        lbm_set_sponge(self.ctx, level, chi, rho_ref, u_ref)
+        return self
 
     def totals(self, level=0, out=None):
         """(sum of rho - rho0, momentum x, y, z) over the updated cells, 4

@@ -472,6 +472,65 @@ void ora_collide_bgk(int lattice, const double* f, double tau, double chi,
   }
 }
 
+/* Multiple-relaxation-time collision on D2Q9 (Lallemand & Luo, Phys. Rev. E
+ * 61, 6546, 2000), one of the comparators of Sec. II.A.  The nine moments
+ * are projections on the orthogonal polynomials of the velocity
+ *   1, e = -4 + 3|xi|^2, eps = 4 - 21/2 |xi|^2 + 9/2 |xi|^4, xi_x,
+ *   q_x = (-5 + 3|xi|^2) xi_x, xi_y, q_y, xi_x^2 - xi_y^2, xi_x xi_y;
+ * their equilibria are those of the second-order equilibrium (e = -2 rho
+ * + 3 |j|^2/rho, eps = rho - 3 |j|^2/rho, q = -j, p_xx = (jx^2 - jy^2)/rho,
+ * p_xy = jx jy / rho); each relaxes at its own rate s[k] and the
+ * populations follow from the orthogonal projection.  s: rates of
+ * (e, eps, q, nu); s_nu = 1/tau sets the viscosity. */
+void ora_collide_mrt(const double* f, const double* s4, double* post) {
+  ora_lattice L;
+  double m[9] = {0}, meq[9], rate[9], norm[9] = {0};
+  double poly[9][9];
+  double rho, jx, jy, jj;
+  int i, k;
+  if (ora_make_lattice(9, &L)) return;
+  for (i = 0; i < 9; ++i) {
+    double x = L.xi[i][0], y = L.xi[i][1], e2 = x * x + y * y;
+    poly[0][i] = 1.0;
+    poly[1][i] = -4.0 + 3.0 * e2;
+    poly[2][i] = 4.0 - 10.5 * e2 + 4.5 * e2 * e2;
+    poly[3][i] = x;
+    poly[4][i] = (-5.0 + 3.0 * e2) * x;
+    poly[5][i] = y;
+    poly[6][i] = (-5.0 + 3.0 * e2) * y;
+    poly[7][i] = x * x - y * y;
+    poly[8][i] = x * y;
+  }
+  for (k = 0; k < 9; ++k)
+    for (i = 0; i < 9; ++i) {
+      m[k] += poly[k][i] * f[i];
+      norm[k] += poly[k][i] * poly[k][i];
+    }
+  rho = m[0];
+  jx = m[3];
+  jy = m[5];
+  jj = jx * jx + jy * jy;
+  meq[0] = rho;
+  meq[1] = -2.0 * rho + 3.0 * jj / rho;
+  meq[2] = rho - 3.0 * jj / rho;
+  meq[3] = jx;
+  meq[4] = -jx;
+  meq[5] = jy;
+  meq[6] = -jy;
+  meq[7] = (jx * jx - jy * jy) / rho;
+  meq[8] = jx * jy / rho;
+  rate[0] = rate[3] = rate[5] = 0.0;
+  rate[1] = s4[0];
+  rate[2] = s4[1];
+  rate[4] = rate[6] = s4[2];
+  rate[7] = rate[8] = s4[3];
+  for (i = 0; i < 9; ++i) {
+    double d = 0.0;
+    for (k = 0; k < 9; ++k) d += poly[k][i] * rate[k] * (m[k] - meq[k]) / norm[k];
+    post[i] = f[i] - d;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the k-th output (k >= 0) of */
 /* the generator seeded with `seed`.  Used for the inlet perturbation.       */
@@ -515,6 +574,10 @@ typedef struct {
   const double* sp_chi;
   const double* sp_rho;
   const double* sp_u;
+  /* collision of FLUID cells: 0 the regularized operator (eq. optimizedLB);
+   * 1 LBM-BGK (eq. standardLB); 2 LBM-MRT on D2Q9 (the comparators of
+   * Sec. II.A); initial and inlet states are the regularized ones */
+  int collision;
 } ora_grid;
 
 /* Sponge strength chi(x) = chi_max * max over faces of the polynomial
@@ -701,6 +764,18 @@ void ora_step_ex(const ora_grid* g, const uint8_t* mask, const uint8_t* skip,
           if (L.d == 2) uref[2] = 0.0;
           for (i = 0; i < L.q; ++i)
             f[i] = ora_pull(g, &L, mask, fin, x, y, z, i);
+          if (g->collision == 1) {
+            ora_collide_bgk(g->lattice, f, g->tau, chi, rref, uref, post);
+            for (i = 0; i < L.q; ++i) fout[(int64_t)i * N + c] = post[i];
+            continue; /* no moment record (comparators run unrefined) */
+          }
+          if (g->collision == 2) {
+            /* Lallemand & Luo's rates for e, eps and q; s_nu = 1/tau */
+            const double s4[4] = {1.64, 1.54, 1.9, 1.0 / g->tau};
+            ora_collide_mrt(f, s4, post);
+            for (i = 0; i < L.q; ++i) fout[(int64_t)i * N + c] = post[i];
+            continue;
+          }
           ora_collide_cell(&L, f, g->tau, chi, rref, uref, post, &rs, us, a2p);
           if (rho_out) rho_out[c] = rs;
           if (u_out)

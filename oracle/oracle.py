@@ -39,6 +39,7 @@ def lib():
         L.ora_splitmix64.restype = C.c_uint64
         L.ora_sponge_chi.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64]
         L.ora_sponge_chi.restype = C.c_double
+        L.ora_collide_mrt.argtypes = [dp, dp, dp]
         L.ora_sponge_sigma.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_sponge_sigma.restype = C.c_double
         L.ora_init.argtypes = [C.c_void_p, dp, dp, dp, dp]
@@ -81,6 +82,7 @@ class OraGrid(C.Structure):
         ("seed", C.c_uint64), ("inlet_noise", C.c_double), ("full_order", C.c_int),
         ("levels", C.c_int),
         ("sp_chi", C.c_void_p), ("sp_rho", C.c_void_p), ("sp_u", C.c_void_p),
+        ("collision", C.c_int),
     ]
 
 
@@ -95,6 +97,20 @@ def lattice(q):
         raise ValueError("unknown lattice %r" % q)
     return (np.array(xi[:], dtype=np.int64).reshape(q, 3), np.array(w[:]),
             np.array(opp[:], dtype=np.int64))
+
+
+# collision of FLUID cells: the regularized operator of eq. (optimizedLB),
+# or the comparators of Sec. II.A: LBM-BGK (eq. standardLB) and LBM-MRT
+# (D2Q9, Lallemand & Luo 2000)
+COLLISIONS = {"rr": 0, "bgk": 1, "mrt": 2}
+
+
+def collide_mrt(f, rates):
+    """D2Q9 MRT collision of one cell with rates (s_e, s_eps, s_q, s_nu)."""
+    f = _f64(f, 9)
+    out = np.zeros(9)
+    lib().ora_collide_mrt(_dp(f), _dp(_f64(rates, 4)), _dp(out))
+    return out
 
 
 def _check_full(q, full):
@@ -183,8 +199,11 @@ class Grid:
     def __init__(self, q, nx, ny, nz=1, tau=0.6, rho0=1.0, u_in=(0.0, 0.0, 0.0),
                  face_bc=(PERIODIC,) * 6, sponge_width=(0,) * 6, chi_max=0.0,
                  rho_ref=1.0, u_ref=(0.0, 0.0, 0.0), seed=0, inlet_noise=0.0,
-                 mask=None, level=0, full_order=False, levels=1):
+                 mask=None, level=0, full_order=False, levels=1, collision="rr"):
         _check_full(q, full_order)
+        if collision not in COLLISIONS or (collision == "mrt" and q != 9) or \
+                (collision != "rr" and full_order):
+            raise ValueError("collision %r on D%dQ%d" % (collision, 2 if q == 9 else 3, q))
         self.q = q
         self.shape = (nx, ny, nz)
         self.N = nx * ny * nz
@@ -200,6 +219,7 @@ class Grid:
         g.seed, g.inlet_noise = seed, inlet_noise
         g.full_order = 1 if full_order else 0
         g.levels = levels
+        g.collision = COLLISIONS[collision]
         self.g = g
         self._sponge = None
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)

@@ -101,6 +101,15 @@ enum {
 #define LBM_NO_GRAPH 0x2u      /* never replay step sequences as hipGraphs */
 #define LBM_SPONGE_FIELD 0x8u  /* reserve per-cell absorbing-layer storage
                                   (lbm_set_sponge) on every level */
+#define LBM_BGK 0x10u          /* comparator collision (Sec. II.A): LBM-BGK,
+                                  eq. (standardLB) with the second-order
+                                  equilibrium, same sponge force; FLUID cells
+                                  only (initial and inlet states stay the
+                                  regularized ones); no refinement */
+#define LBM_MRT 0x20u          /* comparator collision: D2Q9 LBM-MRT of
+                                  Lallemand & Luo (2000) with rates 1.64,
+                                  1.54, 1.9 and 1/tau; no sponge, no
+                                  refinement */
 #define LBM_FULL_ORDER 0x4u    /* full recursive regularization (Sec. II.A,
                                   order n > 2): every Hermite polynomial the
                                   lattice resolves, up to fourth order on
@@ -132,7 +141,7 @@ typedef struct lbm_config {
   double inlet_noise;    /* relative inlet velocity noise amplitude */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
   uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER |
-                            LBM_SPONGE_FIELD */
+                            LBM_SPONGE_FIELD | LBM_BGK | LBM_MRT */
   uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
   int32_t nest_count;    /* further nested boxes, 0 .. LBM_MAX_LEVELS - 2
                             (needs refine_lo/hi) */

@@ -117,6 +117,31 @@ __device__ __forceinline__ void pull_periodic(const SweepArgs<S>& a, uint32_t c,
   });
 }
 
+// Refinement records of one cell's pre-collision moments: on the parent
+// side the nodes on the child box's boundary planes, on the child side the
+// band its parent's IMPORT nodes filter.
+template <class L, class S>
+__device__ __forceinline__ void record_moments(const SweepArgs<S>& a,
+                                               const CellMoments<typename S::R>& mo,
+                                               uint32_t x, uint32_t y, uint32_t z, uint32_t c) {
+  const int64_t r =
+      a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
+  if (r >= 0) {
+    a.rec[r] = mo.drho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
+  }
+  if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
+    a.recf[c] = mo.drho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
+  }
+}
+
 // ------------------------------------------------------------------------
 // The sweep: pull-stream + (sponge) + regularized collision + store.
 // kGeneral = false: every face periodic, no mask, no sponge.
@@ -140,8 +165,13 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   if constexpr (!kGeneral) {
     pull_periodic<L, S>(a, c, x, y, z, raw);
     stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
-    rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref,
-                                       base, post);
+    if constexpr (L::kColl == kCollBGK)
+      rho = collide_bgk<L, S>(raw, drho, j, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref, post);
+    else if constexpr (L::kColl == kCollMRT)
+      rho = collide_mrt<L, S>(raw, drho, j, a.omega1, a.rho0, post);
+    else
+      rho = collide_moments<L, R, false>(drho, j, Pm, a.omega1, a.rho0, (R)0, a.rho_ref,
+                                         a.uref, base, post);
   } else {
     // a plain tile (wave-uniform, read through the scalar cache) needs no
     // mask; otherwise the interior pull is issued before the mask decides:
@@ -155,7 +185,9 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
     const uint8_t kind = m & kKindBits;
     if (kind == kSolid || kind >= kCovered) return;
     // one rebuild for every kind of cell keeps the kernel's code compact
+    // (the comparators collide without it)
     Coeffs<L, R> cf;
+    bool rebuild = true;
     if (kind == kInlet) {
       // f^{eqH}(rho0, U u_dir (1 + noise r)), r from SplitMix64
       R u[3];
@@ -183,32 +215,22 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
       } else if (a.chi_max != (R)0) {
         chi = sponge_chi<R>(a.sponge, a.chi_max, x, y, z, a.nx, a.ny, a.nz);
       }
-      // (the moments are always returned in registers; a conditional
-      // pointer here would push them to scratch memory)
-      CellMoments<R> mo;
-      rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, rref, uref, cf, &mo);
-      if (a.rec || a.recf) {
-        // parent side: moments on the child box's boundary planes
-        const int64_t r =
-            a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
-        if (r >= 0) {
-          a.rec[r] = mo.drho;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
-        }
-        // child side: moments in the band the parent's IMPORT nodes filter
-        if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
-          a.recf[c] = mo.drho;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
-        }
+      if constexpr (L::kColl == kCollBGK) {
+        rho = collide_bgk<L, S>(raw, drho, j, a.omega1, a.rho0, chi, rref, uref, post);
+        rebuild = false;
+      } else if constexpr (L::kColl == kCollMRT) {
+        rho = collide_mrt<L, S>(raw, drho, j, a.omega1, a.rho0, post);
+        rebuild = false;
+      } else {
+        // (the moments are always returned in registers; a conditional
+        // pointer here would push them to scratch memory)
+        CellMoments<R> mo;
+        rho = collide_coeffs<L, R, true>(drho, j, Pm, a.omega1, a.rho0, chi, rref, uref, cf,
+                                         &mo);
+        if (a.rec || a.recf) record_moments<L, S>(a, mo, x, y, z, c);
       }
     }
-    rebuild_from<L, R>(cf, base, post);
+    if (rebuild) rebuild_from<L, R>(cf, base, post);
   }
   // stability watchdog: a rare, benign racy store of 1
   if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
@@ -881,6 +903,10 @@ hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
     case 27: return launch_sweep_l<Lattice<27>>(h, storage, block, st);
     case kFullOrderCode + 9: return launch_sweep_l<Lattice<9, true>>(h, storage, block, st);
     case kFullOrderCode + 27: return launch_sweep_l<Lattice<27, true>>(h, storage, block, st);
+    case kBgkCode + 9: return launch_sweep_l<Lattice<9, false, kCollBGK>>(h, storage, block, st);
+    case kBgkCode + 19: return launch_sweep_l<Lattice<19, false, kCollBGK>>(h, storage, block, st);
+    case kBgkCode + 27: return launch_sweep_l<Lattice<27, false, kCollBGK>>(h, storage, block, st);
+    case kMrtCode + 9: return launch_sweep_l<Lattice<9, false, kCollMRT>>(h, storage, block, st);
   }
   return hipErrorInvalidValue;
 }
@@ -974,6 +1000,18 @@ static hipError_t batch_dispatch(int variant, bool query, const BatchJob* jobs,
       return batch_l<Lattice<9, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
     case kFullOrderCode + 27:
       return batch_l<Lattice<27, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case kBgkCode + 9:
+      return batch_l<Lattice<9, false, kCollBGK>>(storage, general, query, jobs, hdr, block, grid,
+                                                  st, per);
+    case kBgkCode + 19:
+      return batch_l<Lattice<19, false, kCollBGK>>(storage, general, query, jobs, hdr, block,
+                                                   grid, st, per);
+    case kBgkCode + 27:
+      return batch_l<Lattice<27, false, kCollBGK>>(storage, general, query, jobs, hdr, block,
+                                                   grid, st, per);
+    case kMrtCode + 9:
+      return batch_l<Lattice<9, false, kCollMRT>>(storage, general, query, jobs, hdr, block, grid,
+                                                  st, per);
   }
   return hipErrorInvalidValue;
 }

@@ -611,6 +611,124 @@ __device__ __forceinline__ R collide(const R h[L::Q], R omega1, R rho0, R chi, R
                                         out, mo);
 }
 
+// ------------------------------------------------------------------------
+// Comparator operators (Sec. II.A).  raw: the pulled stored values (f for
+// the plain formats, h = f - w rho0 for the shifted ones); post receives
+// values in the same domain.
+// ------------------------------------------------------------------------
+
+// LBM-BGK, eq. (standardLB) with the second-order equilibrium of eq.
+// (truncatedEq) and the same damping force and modified moments as the
+// regularized operator:
+//   post = f - (f - feq(rho*, u)) / tau + chi (feq(rho_ref, u_ref) - feq(rho*, u)).
+// The equilibria are rebuilt from their Hermite coefficients (second order
+// only); base = omega rho0 for the plain formats carries the rest part of
+// omega feq + chi (fref - feq).
+template <class L, class S>
+__device__ __forceinline__ typename S::R collide_bgk(const typename S::T raw[L::Q],
+                                                     typename S::R drho,
+                                                     typename S::R j[3], typename S::R omega1,
+                                                     typename S::R rho0, typename S::R chi,
+                                                     typename S::R rho_ref,
+                                                     const typename S::R uref[3],
+                                                     typename S::R post[L::Q]) {
+  using R = typename S::R;
+  if (chi != (R)0) {
+    const R k = recip((R)1 + (R)0.5 * chi);
+    drho = (drho + (R)0.5 * chi * (rho_ref - rho0)) * k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) j[a] = (j[a] + (R)0.5 * chi * rho_ref * uref[a]) * k;
+  }
+  const R rho = rho0 + drho;
+  const R irho = recip(rho);
+  const R u[3] = {j[0] * irho, j[1] * irho, L::D == 3 ? j[2] * irho : (R)0};
+  const R omega = (R)1 - omega1;
+  const R e = omega - chi;
+  const R ru[3] = {rho_ref * uref[0], rho_ref * uref[1], rho_ref * uref[2]};
+  Coeffs<L, R> c;
+  c.m0 = e * drho + chi * (rho_ref - rho0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.m1[a] = e * j[a] + chi * ru[a];
+  c.m2[0] = e * j[0] * u[0] + chi * ru[0] * uref[0];
+  c.m2[1] = e * j[1] * u[1] + chi * ru[1] * uref[1];
+  c.m2[2] = e * j[2] * u[2] + chi * ru[2] * uref[2];
+  c.m2[3] = e * j[0] * u[1] + chi * ru[0] * uref[1];
+  c.m2[4] = e * j[0] * u[2] + chi * ru[0] * uref[2];
+  c.m2[5] = e * j[1] * u[2] + chi * ru[1] * uref[2];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) c.m3[k] = (R)0;
+  rebuild_from<L, R>(c, S::kShifted ? (R)0 : omega * rho0, post);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) post[i] += omega1 * (R)raw[i];
+  return rho;
+}
+
+// MRT moment polynomials of D2Q9 (Lallemand & Luo, Phys. Rev. E 61, 6546,
+// 2000) at an integer velocity: e, eps, q_x, q_y, p_xx, p_xy (the
+// conserved rho, j_x, j_y are not relaxed), and their norms sum_i m_k(xi_i)^2.
+constexpr double mrt_poly(const Dir& v, int k) {
+  const double x = v.x, y = v.y, e2 = x * x + y * y;
+  return k == 0   ? -4.0 + 3.0 * e2
+         : k == 1 ? 4.0 - 10.5 * e2 + 4.5 * e2 * e2
+         : k == 2 ? (-5.0 + 3.0 * e2) * x
+         : k == 3 ? (-5.0 + 3.0 * e2) * y
+         : k == 4 ? x * x - y * y
+                  : x * y;
+}
+template <class L>
+constexpr double mrt_norm(int k) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += mrt_poly(L::dir(i), k) * mrt_poly(L::dir(i), k);
+  return s;
+}
+
+// LBM-MRT on D2Q9: each non-conserved moment relaxes towards its value for
+// the second-order equilibrium at its own rate (s_e 1.64, s_eps 1.54,
+// s_q 1.9 from Lallemand & Luo; s_nu = 1/tau), projected back with the
+// orthogonal basis.  Written on deviations: m_k(f) - m_k,eq needs the rest
+// state's moments e = -2 rho0, eps = rho0 only, which cancel against the
+// equilibrium's own rho0 terms.
+template <class L, class S>
+__device__ __forceinline__ typename S::R collide_mrt(const typename S::T raw[L::Q],
+                                                     typename S::R drho,
+                                                     const typename S::R j[3],
+                                                     typename S::R omega1, typename S::R rho0,
+                                                     typename S::R post[L::Q]) {
+  using R = typename S::R;
+  R mh[6] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const R h = decode<S>(raw[i], (R)L::w(i) * rho0);
+    static_for<0, 6>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr double p = mrt_poly(L::dir(i), k);
+      if constexpr (p != 0.0) mh[k] += (R)p * h;
+    });
+  });
+  const R rho = rho0 + drho;
+  const R irho = recip(rho);
+  const R jj = (j[0] * j[0] + j[1] * j[1]) * irho;
+  const R s_nu = (R)1 - omega1;
+  R d[6];
+  d[0] = (R)(1.64 / mrt_norm<L>(0)) * (mh[0] + (R)2 * drho - (R)3 * jj);
+  d[1] = (R)(1.54 / mrt_norm<L>(1)) * (mh[1] - drho + (R)3 * jj);
+  d[2] = (R)(1.9 / mrt_norm<L>(2)) * (mh[2] + j[0]);
+  d[3] = (R)(1.9 / mrt_norm<L>(3)) * (mh[3] + j[1]);
+  d[4] = s_nu * (R)(1.0 / mrt_norm<L>(4)) * (mh[4] - (j[0] * j[0] - j[1] * j[1]) * irho);
+  d[5] = s_nu * (R)(1.0 / mrt_norm<L>(5)) * (mh[5] - j[0] * j[1] * irho);
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    R corr = (R)0;
+    static_for<0, 6>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr double p = mrt_poly(L::dir(i), k);
+      if constexpr (p != 0.0) corr += (R)p * d[k];
+    });
+    post[i] = (R)raw[i] - corr;
+  });
+  return rho;
+}
+
 // Hermite coefficients of f^{eqH}(rho, u) + omega1 f^{neqH}(a2, u) (initial
 // state, inlet cells, refinement interfaces), rho given as its deviation
 // drho from rho0.

@@ -118,12 +118,19 @@ constexpr MultiIndex kHigh3[10] = {
     {{1, 1, 2}}, {{2, 2, 1}}, {{2, 1, 2}}, {{1, 2, 2}},               // 4, 5
     {{2, 2, 2}}};                                                     // 6
 
-// Lattice seen by the kernels: the velocity set plus the regularization
-// order (kFull: every resolved order; otherwise the third).
-template <int Q, bool F = false>
+// Collision of FLUID cells: the regularized operator, or the comparators
+// the paper measures it against (Sec. II.A): LBM-BGK, and LBM-MRT on D2Q9.
+enum : int { kCollRR = 0, kCollBGK = 1, kCollMRT = 2 };
+
+// Lattice seen by the kernels: the velocity set, the regularization order
+// (kFull: every resolved order; otherwise the third) and the collision.
+template <int Q, bool F = false, int C = kCollRR>
 struct Lattice : LatticeSet<Q> {
   static_assert(!F || Q != 19, "full-order regularization needs D2Q9 or D3Q27");
+  static_assert(C != kCollMRT || Q == 9, "the MRT comparator is D2Q9 only");
+  static_assert(C == kCollRR || !F, "comparators have no higher orders");
   static constexpr bool kFull = F;
+  static constexpr int kColl = C;
   static constexpr int KH = !F ? 0 : (Q == 9 ? 1 : 10);
   static constexpr MultiIndex high(int k) { return Q == 9 ? kHigh2[k] : kHigh3[k]; }
 };

@@ -10,6 +10,9 @@ namespace hrlbm {
 // Added to the lattice id (9, 27) to select the full-order regularization
 // in the collision kernels' dispatch.
 constexpr int kFullOrderCode = 1000;
+// Added to the lattice id to select a comparator collision in the sweep
+// (LBM-BGK on every lattice, LBM-MRT on D2Q9).
+constexpr int kBgkCode = 2000, kMrtCode = 3000;
 
 // One sweep of one grid: src -> dst.
 struct SweepHost {

@@ -320,7 +320,7 @@ static int advance(lbm_ctx* ctx, int l, bool record_band, hipStream_t st) {
     h.rec_n = R->rec_n;
   }
   if (record_band) h.recf = ctx->ref[l - 1]->recf;
-  hipError_t e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
+  hipError_t e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
   if (e != hipSuccess) return hip_error(e, "sweep launch");
   L.cur ^= 1;
   L.t += 1;

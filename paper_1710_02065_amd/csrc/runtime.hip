@@ -109,6 +109,15 @@ int validate(const lbm_config* cfg) {
   if (!(c.tau > 0.5) || !std::isfinite(c.tau))
     return set_error(LBM_EINVAL, "tau = %g: nu = cs^2 (tau - 1/2) must be > 0", c.tau);
   if (!(c.rho0 > 0)) return set_error(LBM_EINVAL, "rho0 must be > 0");
+  if ((c.flags & LBM_BGK) && (c.flags & LBM_MRT))
+    return set_error(LBM_EINVAL, "LBM_BGK and LBM_MRT are exclusive");
+  if ((c.flags & (LBM_BGK | LBM_MRT)) && (c.flags & LBM_FULL_ORDER))
+    return set_error(LBM_EINVAL, "the comparator collisions have no LBM_FULL_ORDER");
+  if ((c.flags & (LBM_BGK | LBM_MRT)) && refined(c))
+    return set_error(LBM_EINVAL, "the comparator collisions run unrefined");
+  if ((c.flags & LBM_MRT) &&
+      (c.lattice != LBM_D2Q9 || c.chi_max != 0.0 || (c.flags & LBM_SPONGE_FIELD)))
+    return set_error(LBM_EINVAL, "LBM_MRT: D2Q9 without sponge");
   if ((c.flags & LBM_FULL_ORDER) && c.lattice == LBM_D3Q19)
     return set_error(LBM_EINVAL, "LBM_FULL_ORDER needs D2Q9 or D3Q27 (D3Q19 resolves third order only)");
   if (!(c.ma >= 0) || (c.ma > 0.6 && !(c.flags & LBM_ALLOW_HIGH_MA)))
@@ -362,7 +371,7 @@ int check_ready(const lbm_ctx* ctx) {
 int sweep_level(lbm_ctx* ctx, int l, hipStream_t st) {
   Level& L = ctx->lv[l];
   SweepHost h = sweep_args(ctx, l, L.cur, (uint64_t)(L.t + 1));
-  hipError_t e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
+  hipError_t e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
   if (e != hipSuccess) return hip_error(e, "sweep launch");
   L.cur ^= 1;
   L.t += 1;
@@ -417,7 +426,7 @@ static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
     int buf = L.cur;
     for (int64_t s = 0; s < kGraphSteps; ++s) {
       SweepHost h = sweep_args(ctx, 0, buf, (uint64_t)(L.t + 1 + s));
-      e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
+      e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
       if (e != hipSuccess) break;
       buf ^= 1;
     }

@@ -79,6 +79,12 @@ namespace hrlbm {
 inline int kernel_lattice(const lbm_config& c) {
   return c.lattice + ((c.flags & LBM_FULL_ORDER) ? kFullOrderCode : 0);
 }
+// Lattice code of the sweep: kernel_lattice, or a comparator collision.
+inline int sweep_lattice(const lbm_config& c) {
+  if (c.flags & LBM_BGK) return c.lattice + kBgkCode;
+  if (c.flags & LBM_MRT) return c.lattice + kMrtCode;
+  return kernel_lattice(c);
+}
 
 int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);

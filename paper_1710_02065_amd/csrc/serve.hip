@@ -121,7 +121,7 @@ static int graph_for(BatchRunner* r, int variant, int block, int grid, GraphEntr
 // Batch kernel variant of a context: lattice code, storage, sweep path.
 static int batch_variant(const lbm_ctx* c) {
   const SweepHost h = sweep_args(c, 0, 0, 0);
-  return kernel_lattice(c->cfg) * 16 + c->cfg.storage * 2 + (h.general ? 1 : 0);
+  return sweep_lattice(c->cfg) * 16 + c->cfg.storage * 2 + (h.general ? 1 : 0);
 }
 
 // One batch of contexts sharing a kernel variant and workgroup size.
@@ -263,7 +263,7 @@ std::string tune_key(const lbm_ctx* ctx) {
   for (int64_t n = L.N; n > 1; n >>= 2) ++cls;  // log4 of the cell count
   const SweepHost h = sweep_args(ctx, 0, 0, 0);
   char buf[128];
-  std::snprintf(buf, sizeof buf, "%s/q%d/s%d/%s/n4^%d", arch.c_str(), kernel_lattice(ctx->cfg),
+  std::snprintf(buf, sizeof buf, "%s/q%d/s%d/%s/n4^%d", arch.c_str(), sweep_lattice(ctx->cfg),
                 ctx->cfg.storage, h.general ? "general" : "periodic", cls);
   return buf;
 }
@@ -335,13 +335,13 @@ int lbm_autotune(lbm_ctx* ctx, int trials) {
   float best_ms = 1e30f;
   int best = ctx->block;
   for (int blk : cands) {
-    e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
+    e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
     if (e != hipSuccess) break;
     float tot = 0.f;
     for (int t = 0; t < trials && e == hipSuccess; ++t) {
       e = hipEventRecord(a, ctx->stream);
       for (int k = 0; k < reps && e == hipSuccess; ++k)
-        e = launch_sweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
+        e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;

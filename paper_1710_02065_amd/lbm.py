@@ -22,6 +22,7 @@ LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER, LBM_SPONGE_FIELD = 0x1, 0x2, 0x4, 0x8
+LBM_BGK, LBM_MRT = 0x10, 0x20
 LBM_MAX_LEVELS = 5
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S}

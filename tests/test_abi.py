@@ -129,3 +129,15 @@ def test_nested_box_validation():
     assert "box 1" in lbm.lbm_last_error()
     cfg = lbm.make_config(lattice=9, shape=(48, 40, 1), nest=[((4, 4, 0), (20, 20, 0))])
     assert lbm.lbm_required_bytes(cfg) == 0
+
+
+def test_comparator_collisions_validation():
+    assert required(lattice=9, shape=(16, 16, 1), flags=lbm.LBM_MRT) > 0
+    assert required(lattice=19, shape=(16, 16, 16), flags=lbm.LBM_MRT) == 0
+    assert required(lattice=19, shape=(16, 16, 16), flags=lbm.LBM_BGK) > 0
+    assert required(lattice=27, shape=(16, 16, 16), flags=lbm.LBM_BGK | lbm.LBM_FULL_ORDER) == 0
+    assert required(lattice=9, shape=(16, 16, 1), flags=lbm.LBM_BGK | lbm.LBM_MRT) == 0
+    assert required(lattice=9, shape=(32, 32, 1), flags=lbm.LBM_BGK, refine_lo=(8, 8, 0),
+                    refine_hi=(20, 20, 0)) == 0
+    assert required(lattice=9, shape=(32, 32, 1), flags=lbm.LBM_MRT, chi_max=0.1,
+                    sponge_width=(0, 4, 0, 0, 0, 0), face_bc=(2, 2, 0, 0, 0, 0)) == 0

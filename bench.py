@@ -248,6 +248,11 @@ def other_configs(lbm, torch, steps, shedding_steps):
         res["d2q9_cylinder_2048x1024_shedding"]["probes"] = (
             "p = cs^2 rho every 10 steps at r = 1.5, 2, 3, 4 D along 90 and 78.2 degrees")
         torch.cuda.empty_cache()
+    # stability of the collision operators (Sec. II.A): smallest stable tau
+    # on a D2Q9 128^2 thick shear layer at Ma 0.2
+    from paper_1710_02065_amd import stability_study
+    res["d2q9_shear_layer_stability"] = stability_study.run(n=128, ma=0.2, log=log)
+    torch.cuda.empty_cache()
     # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
     # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]
     shape = (384, 256, 256)

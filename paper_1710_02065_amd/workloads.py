@@ -85,6 +85,20 @@ def plane_pulse(nx, ny, nz=1, amp=1e-4, sigma=8.0, x0=None, rho0=1.0):
     return rho, np.zeros((3, nx * ny * nz))
 
 
+def double_shear_layer(n, U, width=80.0, delta=0.05):
+    """Doubly periodic thick shear layer on an n x n box (Brown & Minion
+    1995): u_x = U tanh(width (y/n - 1/4)) below the middle and
+    U tanh(width (3/4 - y/n)) above, u_y = delta U sin(2 pi (x/n + 1/4)),
+    uniform density.  Returns rho [N], u [3][N]."""
+    x, y, _ = _grid(n, n)
+    yn, xn = y / n, x / n
+    u = np.zeros((3, n * n))
+    u[0] = np.where(yn <= 0.5, U * np.tanh(width * (yn - 0.25)),
+                    U * np.tanh(width * (0.75 - yn)))
+    u[1] = delta * U * np.sin(2 * math.pi * (xn + 0.25))
+    return np.ones(n * n), u
+
+
 def shear_wave(nx, ny, nz, amp, k_axis=0, u_axis=1, advect=(0.0, 0.0, 0.0), mode=1):
     """Sinusoidal shear wave u_{u_axis} = amp sin(2 pi mode s / n_s) varying
     along k_axis, on top of a uniform velocity `advect`."""

@@ -1,0 +1,87 @@
+"""Host-side absorbing-layer builders (product helpers for lbm_set_sponge)
+against the oracle's layer profile and the closed forms of a round jet's
+similarity solution."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1710_02065_amd import layers
+
+
+def test_profile_matches_oracle_and_its_shape():
+    s = np.linspace(-3.0, 25.0, 113)
+    p = layers.profile(s, 2.0, 20.0)
+    ref = np.array([O.sponge_sigma(v, 2.0, 20.0) for v in s])
+    assert np.max(np.abs(p - ref)) <= 1e-14
+    # zero at both ends, maximum 1 at four fifths of the layer
+    assert layers.profile(2.0, 2.0, 20.0) == 0.0
+    assert layers.profile(20.0, 2.0, 20.0) == 0.0
+    assert abs(layers.profile(2.0 + 0.8 * 18.0, 2.0, 20.0) - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("shape,center", [((31, 27, 1), (15.0, 13.0, 0.0)),
+                                          ((13, 11, 9), (6.5, 5.0, 4.0))])
+def test_circular_layer_matches_oracle(shape, center):
+    chi = layers.circular_layer(shape, center, 4.0, 14.0, 0.3)
+    ref = O.circular_sponge(shape, center, 4.0, 14.0, 0.3)
+    assert chi.shape == (int(np.prod(shape)),)
+    assert np.max(np.abs(chi - ref)) <= 1e-15
+
+
+def test_jet_reference_similarity_invariants():
+    """Far field of the round jet: centreline speed ~ 1/(s - x0 D), velocity
+    half of it at r = S (s - x0 D), and momentum flux 2 pi int u^2 r dr the
+    same at every station (the similarity solution conserves it)."""
+    D, U, S, x0, B = 8.0, 0.1, 0.094, -3.0, 5.8
+    n = 161
+    shape = (400, n, n)
+    c = (n - 1) / 2.0
+    # cells on one radial line per station: y = c .. n-1, z = c
+    N = shape[0] * n * n
+    rho, u = layers.jet_reference(shape, D, U, S=S, x0=x0, B=B)
+    assert rho.shape == (N,) and u.shape == (3, N)
+    assert np.all(u[1] == 0.0) and np.all(u[2] == 0.0)
+    ua = u[0].reshape(n, n, shape[0])  # [z][y][x]
+    flux, exact = [], []
+    a = (math.sqrt(2.0) - 1.0) / (S * S)
+    for s in (60, 120, 240, 380):
+        xe = s - x0 * D
+        assert abs(ua[int(c), int(c), s] - B * U * D / xe) <= 1e-15
+        r = np.arange(0, n - int(c))
+        line = ua[int(c), int(c):, s]
+        # half-width: u(r_half) = U_c / 2 within the closed form
+        r_half = S * xe
+        assert abs(1.0 / (1.0 + a * (r_half / xe) ** 2) ** 2 - 0.5) <= 1e-12
+        prof = line / line[0]
+        assert np.all(np.diff(prof) <= 0.0)
+        # momentum flux by the trapezoid rule on the radial line
+        flux.append(2.0 * math.pi * np.trapezoid(line ** 2 * r, r))
+        # closed form of the same integral cut at the last cell R:
+        # pi U_c^2 xe^2 / (3 a) (1 - (1 + a R^2 / xe^2)^-3)
+        R = float(r[-1])
+        cut = 1.0 - (1.0 + a * R * R / (xe * xe)) ** -3
+        exact.append(math.pi * (B * U * D) ** 2 / (3.0 * a) * cut)
+    flux, exact = np.array(flux), np.array(exact)
+    # the trapezoid rule's error is second order in cell / half-width
+    err = np.abs(flux / exact - 1.0)
+    assert np.max(err) <= 4e-3
+    assert abs(err[0] / err[1] - ((120 - x0 * D) / (60 - x0 * D)) ** 2) <= 0.05
+    # and without the cut the flux is the same at every station
+    total = math.pi * (B * U * D) ** 2 / (3.0 * a)
+    assert np.max(np.abs(exact[:2] / total - 1.0)) <= 1e-3
+
+
+def test_jet_reference_core_and_inlet_offset():
+    D, U = 6.0, 0.08
+    shape = (60, 31, 1)
+    rho, u = layers.jet_reference(shape, D, U, inlet=(4.0, 15.0), rho_ref=1.02)
+    assert np.all(rho == 1.02)
+    ua = u[0].reshape(31, 60)
+    # inside the potential core: U within half a diameter of the axis, 0 outside
+    assert ua[15, 10] == U and ua[17, 10] == U and ua[15 + 4, 10] == 0.0
+    # upstream of the inlet plane too (s < 0 is part of the core region)
+    assert ua[15, 0] == U
+    # never faster than the exit velocity
+    assert np.max(ua) <= U

@@ -54,11 +54,22 @@ extern "C" {
 /* lattices (Sec. II.A Gauss-Hermite quadratures) */
 enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
 
-/* population storage.  F64: FP64 storage and FP64 arithmetic (verification
+/* state storage.  F64: FP64 storage and FP64 arithmetic (verification
  * build).  F32: FP32 storage of f.  F32S / F16S: FP32 / IEEE binary16
  * storage of the shifted value f_i - w_i rho0 (round to nearest even).
- * Every non-F64 format computes in FP32 on the deviation from rest. */
-enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3 };
+ * Every non-F64 format computes in FP32 on the deviation from rest.
+ * M64 / M32 (FP64 / FP32 storage and arithmetic): instead of the q
+ * populations, the moments of the post-collision state, rho - rho0, u and
+ * a2* = Pi* - rho cs^2 I - rho u u (10 values per cell, 6 on D2Q9), from
+ * which the regularized post-collision populations are rebuilt exactly
+ * (eqs. eqH, neqH, recursive1, recursive2: every Hermite coefficient is a
+ * function of rho, u and the non-equilibrium stress).  Only for fully
+ * periodic, unrefined grids without absorbing layer, mask or comparator
+ * collision (LBM_EINVAL otherwise); not batchable (lbm_step_batch:
+ * LBM_EUNSUPPORTED).  lbm_get_populations rebuilds the populations;
+ * lbm_set_populations keeps a regularized state exactly and projects any
+ * other onto (rho, u, a2*); lbm_force is zero (no SOLID cells). */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_M64 = 4, LBM_M32 = 5 };
 
 /* face rules, per face in the order x-, x+, y-, y+, z-, z+.  Both faces of
  * an axis are periodic or neither is.
@@ -142,7 +153,9 @@ typedef struct lbm_config {
   void* stream;          /* hipStream_t for all work; NULL = null stream */
   uint32_t flags;        /* LBM_ALLOW_HIGH_MA | LBM_NO_GRAPH | LBM_FULL_ORDER |
                             LBM_SPONGE_FIELD | LBM_BGK | LBM_MRT */
-  uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned */
+  uint32_t block;        /* threads per workgroup for the sweep; 0 = tuned.
+                            Moment storages: planes one workgroup marches
+                            through = block / 16 (4 .. 64) */
   int32_t nest_count;    /* further nested boxes, 0 .. LBM_MAX_LEVELS - 2
                             (needs refine_lo/hi) */
   int32_t nest_reserved; /* 0 */

@@ -12,7 +12,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["kernels.hip", "runtime.hip", "refine.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "msweep.hip", "runtime.hip", "refine.hip", "serve.hip"]
 ARCH = os.environ.get("HRLBM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -13,6 +13,9 @@ constexpr int kFullOrderCode = 1000;
 // Added to the lattice id to select a comparator collision in the sweep
 // (LBM-BGK on every lattice, LBM-MRT on D2Q9).
 constexpr int kBgkCode = 2000, kMrtCode = 3000;
+// Storage codes of the moment-stored state (LBM_M64, LBM_M32 in lbm.h).
+constexpr int kM64 = 4, kM32 = 5;
+inline bool moment_storage(int storage) { return storage == kM64 || storage == kM32; }
 
 // One sweep of one grid: src -> dst.
 struct SweepHost {
@@ -244,5 +247,18 @@ hipError_t launch_ring(int lattice, int storage, const RingArgs& a, uint32_t n,
                        hipStream_t st);
 hipError_t launch_import(int lattice, int storage, const ImportArgs& a, uint32_t n,
                          hipStream_t st);
+
+// Moment-stored state (msweep.hip): the sweep (`block` / 16 planes per
+// workgroup) and the companion kernels.
+hipError_t launch_msweep(int lattice, int storage, const SweepHost& h, int block,
+                         hipStream_t st);
+hipError_t launch_minit(int lattice, int storage, const InitArgs& a, hipStream_t st);
+hipError_t launch_mmoments(int lattice, int storage, const MomentArgs& a, hipStream_t st);
+hipError_t launch_mprobe(int storage, const ProbeArgs& a, hipStream_t st);
+hipError_t launch_maccum(int storage, const AccumArgs& a, hipStream_t st);
+hipError_t launch_mtotals(int lattice, int storage, const ReduceArgs& a, hipStream_t st);
+hipError_t launch_mforce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_mget_pop(int lattice, int storage, const PopArgs& a, hipStream_t st);
+hipError_t launch_mset_pop(int lattice, int storage, const PopArgs& a, hipStream_t st);
 
 }  // namespace hrlbm

@@ -46,8 +46,16 @@ size_t storage_bytes(int storage) {
     case LBM_F32:
     case LBM_F32S: return 4;
     case LBM_F16S: return 2;
+    case LBM_M64: return 8;
+    case LBM_M32: return 4;
   }
   return 0;
+}
+
+// stored values per cell: q populations, or the moments of a moment storage
+static int values_per_cell(int lattice, int storage) {
+  if (moment_storage(storage)) return lattice == LBM_D2Q9 ? 6 : 10;
+  return lattice;
 }
 
 // Population stride: a multiple of 128 elements, plus a pad (128 elements
@@ -150,6 +158,19 @@ int validate(const lbm_config* cfg) {
                      LBM_MAX_LEVELS - 2);
   if (c.nest_count > 0 && !refined(c))
     return set_error(LBM_EINVAL, "nested boxes need the level-1 box refine_lo/hi");
+  if (moment_storage(c.storage)) {
+    // the stored moments rebuild the regularized post-collision state
+    // exactly only where no face rule, wall, layer or interface acts
+    for (int f = 0; f < 6; ++f)
+      if (c.face_bc[f] != LBM_PERIODIC)
+        return set_error(LBM_EINVAL, "moment storage needs every face LBM_PERIODIC");
+    if (refined(c) || c.nest_count > 0)
+      return set_error(LBM_EINVAL, "moment storage runs unrefined");
+    if (c.chi_max != 0.0 || (c.flags & LBM_SPONGE_FIELD))
+      return set_error(LBM_EINVAL, "moment storage has no absorbing layer");
+    if (c.flags & (LBM_BGK | LBM_MRT))
+      return set_error(LBM_EINVAL, "moment storage needs the regularized collision");
+  }
   if (refined(c)) return validate_refinement(c);
   return LBM_OK;
 }
@@ -160,13 +181,13 @@ static void level_layout(Level& L, int lattice, int storage, bool sponge_field) 
   L.q = q;
   L.pstride = pop_stride((uint64_t)L.N);
   const size_t popbytes = align_up(L.pstride * storage_bytes(storage), 256);
-  L.buf_bytes = popbytes * q;
+  L.buf_bytes = popbytes * values_per_cell(lattice, storage);
   L.off_buf[0] = 0;
   L.off_buf[1] = L.buf_bytes;
   L.off_mask = 2 * L.buf_bytes;
   L.off_tiles = align_up(L.off_mask + (size_t)L.N, 256);
   L.off_sponge = align_up(L.off_tiles + (size_t)(L.N + 63) / 64, 256);
-  const size_t rsz = storage == LBM_F64 ? 8 : 4;
+  const size_t rsz = (storage == LBM_F64 || storage == LBM_M64) ? 8 : 4;
   L.bytes = align_up(L.off_sponge + (sponge_field ? 5 * (size_t)L.N * rsz : 0), 256);
 }
 
@@ -361,6 +382,13 @@ SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
   return h;
 }
 
+hipError_t launch_step_kernel(const lbm_ctx* ctx, const SweepHost& h, int block,
+                              hipStream_t st) {
+  if (moment_storage(ctx->cfg.storage))
+    return launch_msweep(kernel_lattice(ctx->cfg), ctx->cfg.storage, h, block, st);
+  return launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, block, st);
+}
+
 int check_ready(const lbm_ctx* ctx) {
   if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
   if (!ctx->initialised) return set_error(LBM_ESTATE, "lbm_init has not been called");
@@ -371,7 +399,7 @@ int check_ready(const lbm_ctx* ctx) {
 int sweep_level(lbm_ctx* ctx, int l, hipStream_t st) {
   Level& L = ctx->lv[l];
   SweepHost h = sweep_args(ctx, l, L.cur, (uint64_t)(L.t + 1));
-  hipError_t e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, st);
+  hipError_t e = launch_step_kernel(ctx, h, ctx->block, st);
   if (e != hipSuccess) return hip_error(e, "sweep launch");
   L.cur ^= 1;
   L.t += 1;
@@ -426,7 +454,7 @@ static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
     int buf = L.cur;
     for (int64_t s = 0; s < kGraphSteps; ++s) {
       SweepHost h = sweep_args(ctx, 0, buf, (uint64_t)(L.t + 1 + s));
-      e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, ctx->block, ctx->capture_stream);
+      e = launch_step_kernel(ctx, h, ctx->block, ctx->capture_stream);
       if (e != hipSuccess) break;
       buf ^= 1;
     }
@@ -472,6 +500,8 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
   if (level < 0 || level >= ctx->nlevels)
     return set_error(LBM_EINVAL, "level %d of %d", level, ctx->nlevels);
+  if (mask && moment_storage(ctx->cfg.storage))
+    return set_error(LBM_EINVAL, "moment storage has no cell mask (every cell FLUID)");
   int rc = ensure_device(ctx);
   if (rc != LBM_OK) return rc;
   rc = ensure_memory(ctx);
@@ -496,7 +526,9 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   a.rho0 = ctx->cfg.rho0;
   a.omega1 = 1.0 - 1.0 / L.tau;
   for (int k = 0; k < 3; ++k) a.uin[k] = ctx->uin[k];
-  e = launch_init(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  e = moment_storage(ctx->cfg.storage)
+          ? launch_minit(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, ctx->stream)
+          : launch_init(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "init launch");
   // any level that is not a fully periodic, sponge-free, unrefined grid
   // keeps a mask (all FLUID if none was given) with the flag bits
@@ -611,7 +643,10 @@ int lbm_moments(lbm_ctx* ctx, int level, double* rho_out, double* u_out) {
   a.ncell = (uint32_t)L.N;
   a.pstride = L.pstride;
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_moments(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  hipError_t e = moment_storage(ctx->cfg.storage)
+                     ? launch_mmoments(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, ctx->stream)
+                     : launch_moments(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N,
+                                      ctx->stream);
   if (e != hipSuccess) return hip_error(e, "moments launch");
   if (ctx->unstable) return set_error(LBM_EUNSTABLE, "non-finite or non-positive density seen");
   return LBM_OK;
@@ -637,7 +672,9 @@ int lbm_probe(lbm_ctx* ctx, int level, const int64_t* cells, int n, double* rho_
   a.ncell = (uint32_t)L.N;
   a.pstride = L.pstride;
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_probe(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)n, ctx->stream);
+  hipError_t e = moment_storage(ctx->cfg.storage)
+                     ? launch_mprobe(ctx->cfg.storage, a, ctx->stream)
+                     : launch_probe(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)n, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "probe launch");
   return LBM_OK;
 }
@@ -659,7 +696,9 @@ int lbm_accumulate(lbm_ctx* ctx, int level, double* sum1, double* sum2) {
   a.ncell = (uint32_t)L.N;
   a.pstride = L.pstride;
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_accum(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  hipError_t e = moment_storage(ctx->cfg.storage)
+                     ? launch_maccum(ctx->cfg.storage, a, ctx->stream)
+                     : launch_accum(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
   if (e != hipSuccess) return hip_error(e, "accumulate launch");
   return LBM_OK;
 }
@@ -728,8 +767,13 @@ static int reduce_level(lbm_ctx* ctx, int level, double* out, bool totals) {
   a.pstride = L.pstride;
   for (int f = 0; f < 6; ++f) a.face[f] = L.face[f];
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = totals ? launch_totals(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream)
-                        : launch_force(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
+  hipError_t e;
+  if (moment_storage(ctx->cfg.storage))
+    e = totals ? launch_mtotals(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, ctx->stream)
+               : launch_mforce(a, ctx->stream);
+  else
+    e = totals ? launch_totals(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream)
+               : launch_force(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
   if (e != hipSuccess) return hip_error(e, totals ? "totals launch" : "force launch");
   return LBM_OK;
 }
@@ -759,7 +803,10 @@ int lbm_get_populations(lbm_ctx* ctx, int level, double* out) {
   a.ncell = (uint32_t)L.N;
   a.pstride = L.pstride;
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_get_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  hipError_t e = moment_storage(ctx->cfg.storage)
+                     ? launch_mget_pop(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, ctx->stream)
+                     : launch_get_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N,
+                                      ctx->stream);
   if (e != hipSuccess) return hip_error(e, "get_populations launch");
   return LBM_OK;
 }
@@ -784,7 +831,10 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
   a.ncell = (uint32_t)L.N;
   a.pstride = L.pstride;
   a.rho0 = ctx->cfg.rho0;
-  hipError_t e = launch_set_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N, ctx->stream);
+  hipError_t e = moment_storage(ctx->cfg.storage)
+                     ? launch_mset_pop(kernel_lattice(ctx->cfg), ctx->cfg.storage, a, ctx->stream)
+                     : launch_set_pop(ctx->cfg.lattice, ctx->cfg.storage, a, (uint32_t)L.N,
+                                      ctx->stream);
   if (e != hipSuccess) return hip_error(e, "set_populations launch");
   if (ctx->nlevels > 1) return refined_after_set(ctx, level);
   return LBM_OK;

@@ -96,6 +96,9 @@ void plan_layout(lbm_ctx* ctx);
 void assign_pointers(lbm_ctx* ctx);
 int ensure_device(const lbm_ctx* ctx);
 int check_ready(const lbm_ctx* ctx);
+// the sweep of one level: the population or the moment-storage kernel
+hipError_t launch_step_kernel(const lbm_ctx* ctx, const SweepHost& h, int block,
+                              hipStream_t st);
 SweepHost sweep_args(const lbm_ctx* ctx, int level, int src_buf, uint64_t t_new);
 int sweep_level(lbm_ctx* ctx, int level, hipStream_t st);
 int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st);

@@ -292,6 +292,8 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
     if (steps[k] < 0) return set_error(LBM_EINVAL, "negative step count for job %d", k);
     if (ctxs[k]->nlevels > 1)
       return set_error(LBM_EUNSUPPORTED, "refined contexts cannot be batched");
+    if (moment_storage(ctxs[k]->cfg.storage))
+      return set_error(LBM_EUNSUPPORTED, "moment-stored contexts cannot be batched");
     if (ctxs[k]->device != ctxs[0]->device || ctxs[k]->stream != ctxs[0]->stream)
       return set_error(LBM_EINVAL, "batched contexts must share device and stream");
     for (int m = 0; m < k; ++m)
@@ -335,13 +337,13 @@ int lbm_autotune(lbm_ctx* ctx, int trials) {
   float best_ms = 1e30f;
   int best = ctx->block;
   for (int blk : cands) {
-    e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
+    e = launch_step_kernel(ctx, h, blk, ctx->stream);
     if (e != hipSuccess) break;
     float tot = 0.f;
     for (int t = 0; t < trials && e == hipSuccess; ++t) {
       e = hipEventRecord(a, ctx->stream);
       for (int k = 0; k < reps && e == hipSuccess; ++k)
-        e = launch_sweep(sweep_lattice(ctx->cfg), ctx->cfg.storage, h, blk, ctx->stream);
+        e = launch_step_kernel(ctx, h, blk, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;

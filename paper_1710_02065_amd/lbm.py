@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
 LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 = 9, 19, 27
-LBM_F64, LBM_F32, LBM_F32S, LBM_F16S = 0, 1, 2, 3
+LBM_F64, LBM_F32, LBM_F32S, LBM_F16S, LBM_M64, LBM_M32 = 0, 1, 2, 3, 4, 5
 LBM_PERIODIC, LBM_FREESLIP, LBM_OUTFLOW = 0, 1, 2
 LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
@@ -25,8 +25,9 @@ LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER, LBM_SPONGE_FIELD = 0x1, 0x2, 0x
 LBM_BGK, LBM_MRT = 0x10, 0x20
 LBM_MAX_LEVELS = 5
 
-STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S}
-STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2}
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S,
+           "m64": LBM_M64, "m32": LBM_M32}
+STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2, LBM_M64: 8, LBM_M32: 4}
 
 # every symbol the header declares
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",

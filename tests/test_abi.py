@@ -141,3 +141,24 @@ def test_comparator_collisions_validation():
                     refine_hi=(20, 20, 0)) == 0
     assert required(lattice=9, shape=(32, 32, 1), flags=lbm.LBM_MRT, chi_max=0.1,
                     sponge_width=(0, 4, 0, 0, 0, 0), face_bc=(2, 2, 0, 0, 0, 0)) == 0
+
+
+def test_moment_storage_validation_and_size():
+    """Moment storages: ten values per cell (six on D2Q9) instead of q, and
+    only on fully periodic, unrefined grids without a layer or comparator."""
+    m = required(lattice=19, shape=(64, 64, 64), storage="m32")
+    f = required(lattice=19, shape=(64, 64, 64), storage="f32")
+    cells = 64 ** 3
+    assert 10 * 4 * 2 * cells <= m < 10 * 4 * 2 * cells * 1.01 + (1 << 20)
+    assert m < f * 0.6
+    assert required(lattice=9, shape=(128, 128, 1), storage="m64") >= 6 * 8 * 2 * 128 * 128
+    assert required(lattice=9, shape=(128, 128, 1), storage="m64") < 7 * 8 * 2 * 128 * 128 + (1 << 20)
+    assert required(lattice=27, shape=(16, 16, 16), storage="m32", flags=lbm.LBM_FULL_ORDER) > 0
+    bad = [dict(face_bc=(2, 2, 0, 0, 0, 0)),
+           dict(refine_lo=(4, 4, 4), refine_hi=(12, 12, 12)),
+           dict(chi_max=0.1, sponge_width=(4, 0, 0, 0, 0, 0)),
+           dict(flags=lbm.LBM_SPONGE_FIELD),
+           dict(flags=lbm.LBM_BGK)]
+    for kw in bad:
+        assert required(lattice=19, shape=(16, 16, 16), storage="m32", **kw) == 0, kw
+        assert "moment storage" in lbm.lbm_last_error()

@@ -1,0 +1,198 @@
+"""Moment-stored state (storages LBM_M64 / LBM_M32) on the GPU against the
+FP64 oracle, through the C ABI.
+
+The moment sweep rebuilds every pulled population from its source cell's
+drho, u and post-collision non-equilibrium stress through LDS tiles with a
+halo, marching plane by plane; the grids below span several tiles in x and
+y and several marching chunks, each with a ragged tail.  Bars: M64 within
+1e-12 normwise of the oracle (the same arithmetic as the population path
+up to rounding order); M32 within 2e-6 for one step from the GPU's own
+state (FP32 arithmetic on deviations, FP32 moments: the bound of the FP32
+population formats).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1710_02065_amd import workloads as W
+from tests.pair import gpu_sim, log, normwise, oracle_grid, run_both
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 2e-6
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dim(q):
+    return 2 if q == 9 else 3
+
+
+# x spans 2-3 tiles of 64 (3D) or 254 (2D) cells with a ragged tail; y
+# spans several 2- or 4-row tiles with a ragged tail; the marching axis
+# several chunks of block / 16 planes with a ragged tail
+RAGGED = {9: (300, 37, 1), 19: (150, 13, 37), 27: (70, 11, 21)}
+
+
+@pytest.mark.parametrize("q,full", [(9, False), (19, False), (27, False), (9, True),
+                                    (27, True)])
+@pytest.mark.parametrize("steps,block", [(0, 256), (1, 256), (7, 64), (7, 1024)])
+def test_moment_storage_parity_f64(q, full, steps, block):
+    shape = RAGGED[q]
+    rho, u, p = W.random_state(shape, seed=60 + q, d=dim(q))
+    case = dict(name="moments", q=q, shape=shape, tau=0.53, full=full)
+    gf, of, _, _ = run_both(case, steps, "m64", rho, u, p, block=block)
+    assert normwise(gf, of) <= F64_TOL
+
+
+@pytest.mark.parametrize("q,shape", [(9, (1, 1, 1)), (9, (1, 5, 1)), (9, (7, 1, 1)),
+                                     (9, (255, 3, 1)), (19, (1, 1, 1)), (19, (2, 3, 1)),
+                                     (19, (65, 5, 2)), (27, (3, 1, 2)), (27, (1, 9, 1))])
+def test_moment_storage_degenerate_shapes_f64(q, shape):
+    rho, u, p = W.random_state(shape, seed=31, d=dim(q))
+    case = dict(name="moments-degenerate", q=q, shape=shape, tau=0.8)
+    gf, of, _, _ = run_both(case, 3, "m64", rho, u, p, block=64)
+    assert normwise(gf, of) <= F64_TOL
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+def test_moment_storage_single_step_f32(q):
+    shape = RAGGED[q]
+    rho, u, p = W.random_state(shape, seed=70 + q, d=dim(q))
+    case = dict(name="moments-f32", q=q, shape=shape, tau=0.52)
+    log("moments m32 single step q=%d" % q)
+    sim = gpu_sim(case, "m32").init(rho, u, p)
+    sim.step(2)
+    f0 = sim.populations().cpu().numpy()
+    sim.step(1)
+    f1 = sim.populations().cpu().numpy()
+    sim.sync()
+    g = oracle_grid(case)
+    g.set_populations(f0)
+    g.t = 2
+    g.step(1)
+    assert normwise(f1, g.f) <= F32_TOL
+
+
+def test_moment_storage_observables_f64():
+    """moments, probes, totals and running sums read the stored moments
+    directly; the force is zero (no SOLID cells)."""
+    q, shape = 19, RAGGED[19]
+    rho, u, p = W.random_state(shape, seed=81, d=3)
+    case = dict(name="moments-observables", q=q, shape=shape, tau=0.57)
+    gf, of, sim, g = run_both(case, 5, "m64", rho, u, p)
+    r_g, u_g = sim.moments()
+    r_o, u_o = g.moments()
+    assert normwise(r_g.cpu().numpy(), r_o) <= F64_TOL
+    assert normwise(u_g.cpu().numpy(), u_o) <= F64_TOL
+    cells = np.array([0, 77, 5000, int(np.prod(shape)) - 1], dtype=np.int64)
+    np.testing.assert_allclose(sim.probe(cells).cpu().numpy(), r_o[cells], rtol=1e-13)
+    tot = sim.totals().cpu().numpy()
+    drho = r_o - 1.0
+    assert abs(tot[0] - drho.sum()) <= 1e-12 * np.abs(drho).sum() + 1e-15
+    j = (r_o[None, :] * u_o).sum(axis=1)
+    assert np.max(np.abs(np.asarray(tot[1:]) - j)) <= 1e-12 * np.abs(r_o * u_o).sum()
+    assert np.all(sim.force().cpu().numpy() == 0.0)
+    s1 = torch.zeros(int(np.prod(shape)), dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    sim.accumulate(s1, s2)
+    sim.accumulate(s1, s2)
+    torch.cuda.synchronize()
+    # (the oracle forms rho - rho0 from rho ~ 1: the population storages'
+    # running-sum bar)
+    assert normwise(s1.cpu().numpy(), 2 * drho) <= 1e-11
+    assert normwise(s2.cpu().numpy(), 2 * drho ** 2) <= 1e-11
+
+
+@pytest.mark.parametrize("storage,tol", [("m64", 1e-13), ("m32", 2e-6)])
+def test_moment_storage_checkpoint_resume(storage, tol):
+    """Exported populations of a regularized state import back to the same
+    moments: resuming from a checkpoint continues the run."""
+    case = dict(name="moments-resume", q=27, shape=(40, 9, 12), tau=0.55)
+    rho, u, p = W.random_state(case["shape"], seed=9, d=3)
+    log("moments resume %s" % storage)
+    a = gpu_sim(case, storage).init(rho, u, p).step(20)
+    fa = a.populations().cpu().numpy()
+    b = gpu_sim(case, storage).init(rho, u, p).step(10)
+    c = gpu_sim(case, storage).init(rho, u, p)
+    c.set_populations(b.populations())
+    c.step(10)
+    assert normwise(c.populations().cpu().numpy(), fa) <= tol
+
+
+def test_moment_storage_graph_replay_and_determinism():
+    from paper_1710_02065_amd import lbm
+    case = dict(name="moments-graph", q=19, shape=(70, 12, 20), tau=0.55)
+    rho, u, p = W.random_state(case["shape"], seed=12, d=3)
+    log("moments graph")
+    a = gpu_sim(case, "m32").init(rho, u, p)
+    b = gpu_sim(case, "m32", flags=lbm.LBM_NO_GRAPH).init(rho, u, p)
+    c = gpu_sim(case, "m32").init(rho, u, p)
+    for n in (200, 70, 64, 3):
+        a.step(n)
+        b.step(n)
+        c.step(n)
+        fa = a.populations().cpu().numpy()
+        np.testing.assert_array_equal(fa, b.populations().cpu().numpy())
+        np.testing.assert_array_equal(fa, c.populations().cpu().numpy())
+    a.sync()
+
+
+def test_moment_storage_autotune_keeps_state(tmp_path, monkeypatch):
+    """The autotuner picks the planes per workgroup; every choice computes
+    each cell with the same arithmetic, so the run is bitwise unchanged."""
+    from paper_1710_02065_amd import lbm
+    monkeypatch.setenv("HRLBM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    case = dict(name="moments-tune", q=19, shape=(64, 16, 40), tau=0.55)
+    rho, u, p = W.random_state(case["shape"], seed=13, d=3)
+    log("moments autotune")
+    a = gpu_sim(case, "m32").init(rho, u, p).step(5)
+    before = a.populations().cpu().numpy()
+    best = lbm.lbm_autotune(a.ctx, 1)
+    assert best in (64, 128, 256, 512, 1024)
+    np.testing.assert_array_equal(a.populations().cpu().numpy(), before)
+    a.step(5)
+    ref = gpu_sim(case, "m32", block=64).init(rho, u, p).step(10)
+    np.testing.assert_array_equal(a.populations().cpu().numpy(), ref.populations().cpu().numpy())
+
+
+def test_moment_storage_refuses_mask_and_batch():
+    from paper_1710_02065_amd import lbm
+    case = dict(name="moments-refuse", q=9, shape=(32, 16, 1), tau=0.6)
+    sim = gpu_sim(case, "m32")
+    mask = torch.zeros(32 * 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lbm.LbmError) as e:
+        sim.init(None, None, None, mask)
+    assert e.value.code == lbm.LBM_EINVAL
+    sim.init()
+    other = gpu_sim(case, "f32").init()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_step_batch([sim.ctx, other.ctx], [2, 2])
+    assert e.value.code == lbm.LBM_EUNSUPPORTED
+
+
+def test_moment_storage_acoustic_accuracy_f32():
+    """D3Q19 Taylor-Green flow with a Gaussian pulse (the headline workload
+    at 48^3): after 300 steps the FP32 moment storage's acoustic pressure
+    stays within 1e-4 (relative L2) of the FP64 population build, which
+    itself matches the oracle to 1e-12."""
+    n = 48
+    rho, u = W.taylor_green_3d(n, 0.1 / math.sqrt(3), pulse_amp=1e-3, pulse_sigma=4.0)
+    case = dict(name="moments-acoustic", q=19, shape=(n, n, n), tau=0.52)
+    log("moments acoustic accuracy")
+    ref = gpu_sim(case, "f64").init(rho, u).step(300)
+    r_ref, _ = ref.moments()
+    m = gpu_sim(case, "m32").init(rho, u).step(300)
+    r_m, _ = m.moments()
+    dp_ref = (r_ref.cpu().numpy() - 1.0) / 3.0
+    dp_m = (r_m.cpu().numpy() - 1.0) / 3.0
+    err = np.linalg.norm(dp_m - dp_ref) / np.linalg.norm(dp_ref)
+    log("m32 acoustic pressure error %.3e" % err)
+    assert err <= 1e-4

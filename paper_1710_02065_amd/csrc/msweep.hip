@@ -40,17 +40,16 @@ struct MState {
   }
 };
 
-// Workgroup tile: TX x TY interior cells of a plane, HX x HY with the halo,
-// NT threads; each thread rebuilds up to KS halo-plane slots.
+// Workgroup tile: TX x TY interior cells of a plane, HX x HY with the
+// halo; one thread per halo-plane slot (NT >= HX HY, whole wavefronts).
 template <class L, class R>
 struct MTile {
-  static constexpr int NT = 256;
-  static constexpr int TX = L::D == 3 ? 64 : NT - 2;
-  static constexpr int TY = L::D == 3 ? (sizeof(R) == 8 ? 2 : 4) : 1;
+  static constexpr int TX = L::D == 3 ? 64 : 254;
+  static constexpr int TY = L::D == 3 ? (sizeof(R) == 8 ? 2 : 8) : 1;
   static constexpr int HX = TX + 2;
   static constexpr int HY = L::D == 3 ? TY + 2 : 1;
   static constexpr int SLOTS = HX * HY;
-  static constexpr int KS = (SLOTS + NT - 1) / NT;
+  static constexpr int NT = (SLOTS + 63) / 64 * 64;
 };
 
 // velocity component along the marching axis, and the in-plane LDS offset
@@ -129,12 +128,15 @@ __device__ __forceinline__ R collide_state(const R h[L::Q], R omega1, R rho0,
 // keeps the parts it will write in the next two iterations in registers.
 // After a barrier every interior cell pulls its q populations from the
 // slots at x - xi, collides and stores its moments; a second barrier
-// protects the LDS plane before it is rewritten.
+// protects the LDS plane before it is rewritten.  The loads are issued
+// for every thread and iteration (threads beyond the halo plane load a
+// valid cell and write nothing), so they stay in flight across the
+// barriers instead of being waited for at a branch.
 // ------------------------------------------------------------------------
 template <class L, class R>
-__global__ void __launch_bounds__(256) k_msweep(const MSweepArgs<R> a) {
+__global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R> a) {
   using G = MTile<L, R>;
-  constexpr int Q = L::Q, NM = MState<L>::NM, KS = G::KS;
+  constexpr int Q = L::Q, NM = MState<L>::NM;
   __shared__ R lds[Q * G::SLOTS];
 
   uint32_t b = blockIdx.x;
@@ -148,24 +150,17 @@ __global__ void __launch_bounds__(256) k_msweep(const MSweepArgs<R> a) {
   const uint32_t wy = L::D == 3 ? min((uint32_t)G::TY, a.py - y0) : 1u;
   const uint32_t m0 = ch * a.zc, m1 = min(a.pm, m0 + a.zc);
   const uint32_t hx = wx + 2, hy = L::D == 3 ? wy + 2 : 1u;
-  const uint32_t nslot = hx * hy;
   const uint32_t plane = a.px * a.py;
   const uint64_t P = a.pstride;
   const uint32_t tid = threadIdx.x;
 
-  // slots this thread rebuilds: plane cell and LDS index
-  uint32_t scell[KS], slds[KS];
-  bool sown[KS];
-#pragma unroll
-  for (int k = 0; k < KS; ++k) {
-    const uint32_t s = tid + (uint32_t)k * G::NT;
-    sown[k] = s < nslot;
-    const uint32_t sx = sown[k] ? s % hx : 0u, sy = sown[k] ? s / hx : 0u;
-    const uint32_t gx = (x0 + sx + a.px - 1) % a.px;
-    const uint32_t gy = L::D == 3 ? (y0 + sy + a.py - 1) % a.py : 0u;
-    scell[k] = gy * a.px + gx;
-    slds[k] = sy * G::HX + sx;
-  }
+  // the slot this thread rebuilds: plane cell and LDS index
+  const bool sown = tid < hx * hy;
+  const uint32_t sx = sown ? tid % hx : 0u, sy = sown ? tid / hx : 0u;
+  const uint32_t gx = (x0 + sx + a.px - 1) % a.px;
+  const uint32_t gy = L::D == 3 ? (y0 + sy + a.py - 1) % a.py : 0u;
+  const uint32_t scell = gy * a.px + gx;
+  const uint32_t slds = sy * G::HX + sx;
   // output cell of this thread
   const uint32_t ox = tid % G::TX, oy = tid / G::TX;
   const bool oown = tid < (uint32_t)(G::TX * G::TY) && ox < wx && oy < wy;
@@ -177,49 +172,39 @@ __global__ void __launch_bounds__(256) k_msweep(const MSweepArgs<R> a) {
   };
 
   // carried parts: up1 = +1 part of plane m - 1, up2 = +1 part of plane m,
-  // mid = 0 part of plane m; nxt = moments of plane m + 1
-  R up1[KS][Q], up2[KS][Q], mid[KS][Q], nxt[KS][NM];
-#pragma unroll
-  for (int k = 0; k < KS; ++k) {
-    if (!sown[k]) continue;
-    R mm[NM], h[Q];
-    load_state<L, R>(a.src, P, wrap_m(m0, -1) * plane + scell[k], mm);
-    rebuild_cell<L, R>(mm, a.rho0, h);
-    static_for<0, Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (march_of<L>(i) > 0) up1[k][i] = h[i];
-    });
-    load_state<L, R>(a.src, P, m0 * plane + scell[k], mm);
-    rebuild_cell<L, R>(mm, a.rho0, h);
-    static_for<0, Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (march_of<L>(i) > 0) up2[k][i] = h[i];
-      if constexpr (march_of<L>(i) == 0) mid[k][i] = h[i];
-    });
-    load_state<L, R>(a.src, P, wrap_m(m0, 1) * plane + scell[k], nxt[k]);
-  }
-
-  for (uint32_t m = m0; m < m1; ++m) {
-#pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      if (!sown[k]) continue;
+  // mid = 0 part of plane m; nxt = moments of plane m + 1.  Two warm-up
+  // iterations fill them through the same code as the others (so every
+  // plane is rebuilt by the same instructions whatever the chunk length).
+  R up1[Q], up2[Q], mid[Q], nxt[NM];
+  load_state<L, R>(a.src, P, wrap_m(m0, -1) * plane + scell, nxt);
+  for (int it = -2; it < (int)(m1 - m0); ++it) {
+    R v[Q];
+    {
       R h[Q];
-      rebuild_cell<L, R>(nxt[k], a.rho0, h);
+      rebuild_cell<L, R>(nxt, a.rho0, h);
+      // moments of plane m0 + it + 2 (wrapped: always a valid plane)
+      load_state<L, R>(a.src, P, wrap_m(m0, it + 2) * plane + scell, nxt);
       static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        R* dst = &lds[i * G::SLOTS + slds[k]];
         if constexpr (march_of<L>(i) > 0) {
-          *dst = up1[k][i];
-          up1[k][i] = up2[k][i];
-          up2[k][i] = h[i];
+          v[i] = up1[i];
+          up1[i] = up2[i];
+          up2[i] = h[i];
         } else if constexpr (march_of<L>(i) == 0) {
-          *dst = mid[k][i];
-          mid[k][i] = h[i];
+          v[i] = mid[i];
+          mid[i] = h[i];
         } else {
-          *dst = h[i];
+          v[i] = h[i];
         }
       });
-      if (m + 1 < m1) load_state<L, R>(a.src, P, wrap_m(m, 2) * plane + scell[k], nxt[k]);
+    }
+    if (it < 0) continue;
+    const uint32_t m = m0 + (uint32_t)it;
+    if (sown) {
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        lds[i * G::SLOTS + slds] = v[i];
+      });
     }
     __syncthreads();
     if (oown) {

@@ -8,10 +8,12 @@ sweep over the whole grid (pull, moments, regularized collision, store).
 
 Prints one JSON line: MLUPS (whole job), the HBM roofline of the sweep kernel
 (algorithmic bytes 2 q sizeof(storage) per cell update over the kernel time
-measured with HIP events on the launch stream), the FP16-shifted storage
-variant with its speedup, the precision of FP32 / FP16-shifted storage
-against the FP64 build (which matches the oracle to 1e-12), and the FP64 CPU
-oracle timed on the host cores on a bounded sample of the same workload.
+measured with HIP events on the launch stream), the other storage forms
+(FP16-shifted, FP32-shifted, FP64, and the moment storages M32 / M64 that
+keep 10 moments per cell instead of 19 populations) with their speedups, the
+precision of each FP32 / 16-bit form against the FP64 build (which matches
+the oracle to 1e-12), and the FP64 CPU oracle timed on the host cores on a
+bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -28,16 +30,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS & % HBM roofline (D3Q19 256³); p50/p99 latency, batched serving"
-SOURCES = ["kernels.hip", "kernels.hpp", "lattice.hpp"]
+# sources each profiled kernel is compiled from
+SOURCES = {"k_sweep": ["kernels.hip", "kernels.hpp", "lattice.hpp"],
+           "k_msweep": ["msweep.hip", "kernels.hpp", "lattice.hpp"]}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(kernel="k_sweep"):
     h = hashlib.sha256()
-    for s in SOURCES:
+    for s in SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1710_02065_amd", "csrc", s), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -55,7 +59,7 @@ def measured_traffic(name):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 d[k.strip()] = v.strip()
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(name.split("_d3q")[0]):
         return None
     return int(d["bytes_per_launch"])
 
@@ -125,12 +129,12 @@ def cpu_baseline(n, seconds):
 
 
 def precision_study(lbm, torch, n, fields, horizons):
-    """FP32, FP32-shifted and FP16-shifted storage run side by side with the
+    """FP32, FP32-shifted, FP16-shifted and FP32-moment storage run side by side with the
     FP64 build (which matches the oracle to 1e-12) on the headline workload;
     relative L2 error of the acoustic pressure p' = cs^2 (rho - rho0) and of
     u at each horizon."""
     sims = {}
-    for st in ("f64", "f32", "f32s", "f16s"):
+    for st in ("f64", "f32", "f32s", "f16s", "m32"):
         sims[st] = lbm.Simulation(lattice=19, shape=(n, n, n), tau=0.52, storage=st)
         sims[st].init(*fields)
     out = {}
@@ -142,7 +146,7 @@ def precision_study(lbm, torch, n, fields, horizons):
         r64, u64 = sims["f64"].moments()
         p64 = (r64 - 1.0) / 3.0
         row = {}
-        for st in ("f32", "f32s", "f16s"):
+        for st in ("f32", "f32s", "f16s", "m32"):
             r, u = sims[st].moments()
             row[st] = dict(p_rel_l2=float((((r - 1.0) / 3.0 - p64).norm() / p64.norm()).item()),
                            u_rel_l2=float(((u - u64).norm() / u64.norm()).item()))
@@ -324,6 +328,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--storage", default="f32", choices=["f32", "m32"],
+                    help="storage of the timed headline run: FP32 populations, or the "
+                         "FP32 moment storage (10 values per cell)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -374,39 +381,46 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    log("timing f32: %d warmup + %d steps" % (args.warmup, args.steps))
-    sim32, ms32 = run_gpu(lbm, torch, "f32", n, args.steps, args.warmup, fields, args.block)
+    hs = args.storage
+    moment = hs == "m32"
+    log("timing %s: %d warmup + %d steps" % (hs, args.warmup, args.steps))
+    sim32, ms32 = run_gpu(lbm, torch, hs, n, args.steps, args.warmup, fields, args.block)
     mlups32 = N * args.steps / (ms32 * 1e3)
-    bytes_lup = 2 * 19 * 4
+    bytes_lup = 2 * (10 if moment else 19) * 4
     per_launch_s = ms32 / 1e3 / args.steps
     wg32 = sim32.block
     achieved = bytes_lup * N / per_launch_s / 1e9
-    traffic = measured_traffic("k_sweep_d3q19_f32_256") if n == 256 else None
+    kname = "k_msweep_d3q19_m32_256" if moment else "k_sweep_d3q19_f32_256"
+    traffic = measured_traffic(kname) if n == 256 else None
 
     variants = {}
     precision = {}
     del sim32
     torch.cuda.empty_cache()
     if not args.no_variants:
-        for st in ("f16s", "f32s", "f64"):
+        for st in [v for v in ("f32", "f16s", "f32s", "f64", "m32", "m64") if v != hs]:
             log("timing %s" % st)
             sv, msv = run_gpu(lbm, torch, st, n, args.steps, args.warmup, fields, args.block)
-            b = 2 * 19 * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
+            # the moment storages move 10 values per cell each way, not 19
+            vals = 10 if st.startswith("m") else 19
+            b = 2 * vals * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
             mv = N * args.steps / (msv * 1e3)
             variants[st] = dict(value=round(mv, 1), unit="MLUPS", bytes_per_lup=b,
                                 hbm_gbs=round(b * N / (msv / 1e3 / args.steps) / 1e9, 1),
-                                speedup_vs_f32=round(mv / mlups32, 3), workgroup=sv.block)
+                                speedup_vs_headline=round(mv / mlups32, 3), workgroup=sv.block)
+            if st.startswith("m"):
+                variants[st]["planes_per_workgroup"] = sv.block // 16
             del sv
             torch.cuda.empty_cache()
         # regularization order on D3Q27 (the lattice that resolves up to sixth
         # order): third order against the full recursive expansion
         order = {}
-        for st in ("f32", "f16s"):
+        for st in ("f32", "f16s", "m32"):
             for name, fl in (("third", 0), ("full", lbm.LBM_FULL_ORDER)):
                 log("timing d3q27 %s %s" % (st, name))
                 sv, msv = run_gpu(lbm, torch, st, n, max(args.steps // 4, 50), args.warmup // 4,
                                   fields, args.block, lattice=27, flags=fl)
-                b = 2 * 27 * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
+                b = 2 * (10 if st.startswith("m") else 27) * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
                 ns = max(args.steps // 4, 50)
                 order["d3q27_%s_%s" % (st, name)] = dict(
                     mlups=round(N * ns / (msv * 1e3), 1), bytes_per_lup=b,
@@ -432,15 +446,16 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "D3Q19 %d^3 periodic, Taylor-Green U=0.1cs + Gaussian pulse 1e-3 "
-                        "sigma 8, tau 0.52, FP32 storage (fused pull + rrBGK sweep)" % n,
-            "lattice": "D3Q19", "cells": N, "storage": "f32", "tau": 0.52,
+                        "sigma 8, tau 0.52, %s (fused pull + rrBGK sweep)"
+                        % (n, "FP32 moment storage" if moment else "FP32 storage"),
+            "lattice": "D3Q19", "cells": N, "storage": hs, "tau": 0.52,
             "parallelism": "single GPU"},
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_lup * N,
-            "kernel": "k_sweep<D3Q19, f32>"},
+            "kernel": "k_msweep<D3Q19, float>" if moment else "k_sweep<D3Q19, f32>"},
     }
     if variants:
         out["variants"] = variants

@@ -50,6 +50,10 @@ struct MTile {
   static constexpr int HY = L::D == 3 ? TY + 2 : 1;
   static constexpr int SLOTS = HX * HY;
   static constexpr int NT = (SLOTS + 63) / 64 * 64;
+  // LDS planes: with two, consecutive iterations alternate and one barrier
+  // per plane suffices (measured slower: the doubled LDS halves the
+  // workgroups a CU holds)
+  static constexpr int NB = 1;
 };
 
 // velocity component along the marching axis, and the in-plane LDS offset
@@ -137,7 +141,7 @@ template <class L, class R>
 __global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R> a) {
   using G = MTile<L, R>;
   constexpr int Q = L::Q, NM = MState<L>::NM;
-  __shared__ R lds[Q * G::SLOTS];
+  __shared__ R lds_all[G::NB * Q * G::SLOTS];
 
   uint32_t b = blockIdx.x;
   if (a.xcd_order) b = (b % 8u) * (a.nblocks / 8u) + b / 8u;
@@ -200,6 +204,7 @@ __global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R
     }
     if (it < 0) continue;
     const uint32_t m = m0 + (uint32_t)it;
+    R* lds = lds_all + (G::NB == 2 ? (uint32_t)(it & 1) * (Q * G::SLOTS) : 0u);
     if (sown) {
       static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -221,7 +226,7 @@ __global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R
       for (int k = 0; k < NM; ++k)
         store_pop_nt(a.dst + (uint64_t)k * P, (uint32_t)(P * sizeof(R)), c, mo[k]);
     }
-    __syncthreads();
+    if constexpr (G::NB == 1) __syncthreads();
   }
 }
 

@@ -306,9 +306,11 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
  * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */
 int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
 
-/* Time the sweep for each candidate workgroup size on this context's
- * current state (the state is restored afterwards), keep the fastest, and
- * return it (> 0) or a negative status. */
+/* Time the sweep for each candidate workgroup size (64, 128, 256, 512,
+ * 1024; for the moment storages the same values select block / 16 planes
+ * per workgroup) on this context's current state (the state is restored
+ * afterwards), keep the fastest, and return it (> 0) or a negative
+ * status. */
 int lbm_autotune(lbm_ctx* ctx, int trials);
 
 /* Release the context and the memory it allocated.  NULL-safe. */

@@ -3,6 +3,8 @@ geometries and references of Sec. III and IV): host-side builders of chi,
 rho_ref and u_ref over a grid's cells (FP64 numpy arrays, cell index
 c = (z ny + y) nx + x).
 
+- face_layer: the planar layers of the faces as a field (to pair with a
+  spatially varying reference);
 - circular_layer: the layer of the cylinder setup, a ring (2D) or shell
   (3D) whose strength follows the profile of Sec. II.C in the distance from
   a centre;
@@ -28,6 +30,23 @@ def _coords(shape):
     c = np.arange(nx * ny * nz)
     return (c % nx).astype(np.float64), ((c // nx) % ny).astype(np.float64), \
         (c // (nx * ny)).astype(np.float64)
+
+
+def face_layer(shape, widths, chi_max):
+    """chi per cell of the planar face layers (the profile the sweep
+    evaluates from the coordinates when no field is given): on face f
+    (x-, x+, y-, y+, z-, z+) of width W the profile over the last W cells,
+    s = distance coordinate from the opposite side, s0 = n - W, L = n;
+    faces combine by their maximum."""
+    pos = _coords(shape)
+    chi = np.zeros(pos[0].size)
+    for f, W in enumerate(widths):
+        if W <= 0:
+            continue
+        ax, n = f // 2, shape[f // 2]
+        s = pos[ax] if f % 2 == 1 else (n - 1) - pos[ax]
+        chi = np.maximum(chi, profile(s, float(n - W), float(n)))
+    return chi_max * chi
 
 
 def circular_layer(shape, center, r0, r1, chi_max):

@@ -198,3 +198,56 @@ def test_three_level_f32_tracks_oracle():
     for l, g in enumerate(og.grids):
         keep = og.crole[l] != 2
         assert normwise(pops[l][:, keep], g.f[:, keep]) <= 2e-6 * 40 ** 0.5, l
+
+
+def test_refined_field_sponge_jet_reference_parity_f64():
+    """Per-cell absorbing layers on a refined jet (Sec. IV: the outflow layer
+    relaxes to the round-jet similarity field): on level 0 the face profile
+    of the x+, y and z faces with the similarity velocity as reference, on
+    level 1 a weak spherical layer; both against the oracle's per-cell
+    layers on its multi-level driver, FP64 within 1e-12."""
+    from paper_1710_02065_amd import layers, lbm
+    shape = (34, 26, 26)
+    mask = W.jet_inlet_mask(*shape, D=6)
+    case = dict(name="ml-field-sponge", q=27, shape=shape, lo=(4, 7, 7), hi=(16, 18, 18),
+                tau=0.53, ma=0.2, seed=5, inlet_noise=0.02, face_bc=(2, 2, 1, 1, 2, 2),
+                masks=[mask, None])
+    from tests.pair import multilevel_pair, multilevel_sim
+    og = multilevel_pair(case)
+    U = 0.2 / math.sqrt(3)
+    # level 0: the face profile of the x+, y-, y+, z-, z+ faces (width 7)
+    chi0 = layers.face_layer(shape, (0, 7, 7, 7, 7, 7), 0.25)
+    rho0, u0 = layers.jet_reference(shape, 6.0, U, inlet=(0.0, None, None), core=2.0,
+                                    rho_ref=1.002)
+    fshape = og.grids[1].shape
+    chi1 = layers.circular_layer(fshape, ((fshape[0] - 1) / 2, (fshape[1] - 1) / 2,
+                                          (fshape[2] - 1) / 2), 6.0, 30.0, 0.1)
+    N1 = int(np.prod(fshape))
+    rho1 = np.full(N1, 0.999)
+    u1 = np.zeros((3, N1))
+    u1[0] = 0.5 * U
+    fields = [W.random_state(g.shape, seed=21 + l, d=3, u_amp=0.03, rho_amp=0.01, pi_amp=5e-4)
+              for l, g in enumerate(og.grids)]
+    log("refined field sponge q=27 levels=2")
+    sim = multilevel_sim(case, "f64", flags=lbm.LBM_SPONGE_FIELD)
+    for l, f in enumerate(fields):
+        sim.init(*f, mask=case["masks"][l], level=l)
+    sim.set_sponge(chi0, rho0, u0, level=0)
+    sim.set_sponge(chi1, rho1, u1, level=1)
+    sim.step(5)
+    pops = [sim.populations(l).cpu().numpy() for l in range(2)]
+    sim.sync()
+    og.grids[0].set_sponge(chi0, rho0, u0)
+    og.grids[1].set_sponge(chi1, rho1, u1)
+    for l, f in enumerate(fields):
+        og.init(l, *f)
+    og.step(5)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+    # the layers acted: without them the run differs
+    ref = multilevel_pair(case)
+    for l, f in enumerate(fields):
+        ref.init(l, *f)
+    ref.step(5)
+    assert normwise(ref.grids[0].f, og.grids[0].f) > 1e-6

@@ -85,3 +85,16 @@ def test_jet_reference_core_and_inlet_offset():
     assert ua[15, 0] == U
     # never faster than the exit velocity
     assert np.max(ua) <= U
+
+
+@pytest.mark.parametrize("shape,widths", [((30, 22, 1), (0, 8, 3, 3, 0, 0)),
+                                          ((17, 13, 11), (2, 5, 0, 4, 3, 3))])
+def test_face_layer_matches_oracle_face_profile(shape, widths):
+    g = O.Grid(9 if shape[2] == 1 else 19, *shape, tau=0.6,
+               face_bc=tuple(2 if w > 0 or widths[f ^ 1] > 0 else 0 for f, w in enumerate(widths)),
+               sponge_width=widths, chi_max=0.3)
+    chi = layers.face_layer(shape, widths, 0.3)
+    ref = np.array([g.chi(x, y, z) for z in range(shape[2]) for y in range(shape[1])
+                    for x in range(shape[0])])
+    assert np.max(np.abs(chi - ref)) <= 1e-15
+    assert chi.max() > 0.2

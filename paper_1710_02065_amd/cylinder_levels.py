@@ -1,0 +1,184 @@
+"""Flow past a cylinder on nested refinement levels, in the arrangement of
+Sec. III: D2Q9, Re 150, Ma 0.2, N cells per diameter on the finest of four
+levels (each level halves the spacing and the time step of its parent,
+Sec. II.B), uniform flow imposed by an absorbing layer that follows a
+circle around the body and covers the corners, outflow faces.
+
+The body (SOLID cells, bounce-back) lives on the finest level, where the
+momentum-exchange force gives C_D, C_L and the Strouhal number; the
+pressure field is sampled on the coarsest level, where the waves travel:
+rms directivity on a ring, the decay of the shedding tone along the
+90-degree ray.
+
+    python -m paper_1710_02065_amd.cylinder_levels [--levels 4 --D 32 ...]
+
+prints one JSON line.  Every step runs in the HIP library.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import acoustics as A
+from . import layers
+from . import lbm
+
+CS = math.sqrt(1.0 / 3.0)
+
+
+def geometry(levels, D, extent, halfwidths, downstream):
+    """Grid of level 0 and the nested boxes.  D cells per diameter on the
+    finest level, D / 2^(levels-1) on level 0 (an integer); level 0 is
+    `extent` diameters square with the body at its centre; the box of level
+    l (l >= 1) spans halfwidths[l-1] diameters upstream and sideways of the
+    body centre and downstream times that behind it, in the coordinates of
+    level l - 1.  Returns (n0, D0, boxes, centres): level-0 side, cells per
+    diameter on level 0, the boxes, and the body centre in the coordinates
+    of each level."""
+    D0 = D // 2 ** (levels - 1)
+    if D0 * 2 ** (levels - 1) != D or D0 < 2:
+        raise ValueError("D must be a multiple of 2^(levels-1) with at least 2 cells on level 0")
+    n0 = int(extent * D0) // 2 * 2 + 1
+    c = [(n0 - 1) // 2, (n0 - 1) // 2]
+    centres, boxes = [tuple(c)], []
+    for l in range(1, levels):
+        Dp = D0 * 2 ** (l - 1)
+        h = int(round(halfwidths[l - 1] * Dp))
+        lo = (c[0] - h, c[1] - h, 0)
+        hi = (c[0] + int(round(downstream * h)), c[1] + h, 0)
+        boxes.append((lo, hi))
+        c = [2 * (c[0] - lo[0]), 2 * (c[1] - lo[1])]
+        centres.append(tuple(c))
+    return n0, D0, boxes, centres
+
+
+def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1.5,
+        ma=0.2, re=150.0, coarse_steps=8000, window=4000, layer_D=(50.0, 115.0),
+        chi_max=0.5, face_layer_D=20.0, face_chi=0.3, storage="f32", seed=2,
+        ring_D=40.0, log=None):
+    import torch
+
+    n0, D0, boxes, centres = geometry(levels, D, extent, halfwidths, downstream)
+    U = ma * CS
+    tau_f = 0.5 + 3.0 * U * D / re          # finest level
+    tau0 = tau_f
+    for _ in range(levels - 1):             # tau_f = 2 tau_c - 1/2 per interface
+        tau0 = (tau0 + 0.5) / 2.0
+    lo1, hi1 = boxes[0]
+    sim = lbm.Simulation(lattice=9, shape=(n0, n0, 1), tau=tau0, storage=storage, ma=ma,
+                         face_bc=(2, 2, 2, 2, 0, 0), rho_ref=1.0, u_ref=(U, 0.0, 0.0),
+                         seed=seed, refine_lo=lo1, refine_hi=hi1, nest=tuple(boxes[1:]),
+                         flags=lbm.LBM_SPONGE_FIELD)
+    dev = sim.device
+    shapes = [sim.shape(l) for l in range(levels)]
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    for l, (nx, ny, _) in enumerate(shapes):
+        N = nx * ny
+        u = torch.zeros(3, N, dtype=torch.float64, device=dev)
+        u[0] = U
+        u[:2] += 1e-4 * U * (2 * torch.rand(2, N, generator=g, device=dev,
+                                             dtype=torch.float64) - 1)
+        mask = None
+        if l == levels - 1:
+            cx, cy = centres[l]
+            y, x = np.mgrid[0:ny, 0:nx]
+            m = ((x - cx) ** 2 + (y - cy) ** 2 <= (D / 2.0) ** 2).astype(np.uint8)
+            mask = torch.from_numpy(m.reshape(-1)).to(dev)
+        sim.init(None, u, None, mask, level=l)
+    # absorbing layer on level 0: circle around the body, joined with a
+    # planar layer at the faces so that the corners are covered
+    cx0, cy0 = centres[0]
+    chi = np.maximum(
+        layers.circular_layer((n0, n0, 1), (cx0, cy0, 0.0), layer_D[0] * D0, layer_D[1] * D0,
+                              chi_max),
+        layers.face_layer((n0, n0, 1), (int(face_layer_D * D0),) * 4 + (0, 0), face_chi))
+    sim.set_sponge(chi, level=0)
+
+    ring_angles = np.arange(30.0, 150.1, 1.0)
+    ring = A.ring_cells(n0, n0, cx0, cy0, ring_D * D0, ring_angles)
+    clear = layer_D[0] * D0
+    ray_r = np.geomspace(2.0 * D0, 0.95 * clear, 32)
+    ray = torch.tensor((cy0 + np.round(ray_r).astype(np.int64)) * n0 + cx0, device=dev)
+    forces = torch.zeros(coarse_steps, 3, dtype=torch.float64, device=dev)
+    probes = torch.zeros(window, len(ray), dtype=torch.float64, device=dev)
+    s1 = torch.zeros(n0 * n0, dtype=torch.float64, device=dev)
+    s2 = torch.zeros_like(s1)
+    t0 = time.time()
+    w0 = coarse_steps - window
+    for s in range(coarse_steps):
+        sim.step(1)
+        sim.force(level=levels - 1, out=forces[s])
+        if s >= w0:
+            lbm.lbm_probe(sim.ctx, 0, ray, probes[s - w0])
+            sim.accumulate(s1, s2, level=0)
+        if log and s % 1000 == 999:
+            log("cylinder levels %d/%d coarse steps %.1fs" % (s + 1, coarse_steps,
+                                                              time.time() - t0))
+    sim.sync()
+    elapsed = time.time() - t0
+    fine_dt = 2 ** (levels - 1)             # fine steps per coarse step
+    cd, cl = A.force_coefficients(forces.cpu().numpy(), 1.0, U, D)
+    cd_w, cl_w = cd[w0:], cl[w0:]
+    # times in fine-level steps: one sample per coarse step
+    st = A.strouhal(cl_w, D, U, dt=fine_dt)
+    f_shed = (st if st else A.peak_frequency(cl_w, fine_dt) * D / U) * U / D
+    rms = A.rms_from_sums(s1.cpu().numpy(), s2.cpu().numpy(), window) * CS * CS
+    p = probes.cpu().numpy() * CS * CS
+    # level-0 samples are one coarse step apart; the tone's frequency there
+    # is f_shed per fine step times fine_dt
+    amp = np.array([A.tone_amplitude(p[:, j], f_shed * fine_dt, 1.0) for j in range(p.shape[1])])
+    lam0 = CS / (f_shed * fine_dt)          # acoustic wavelength in level-0 cells
+    far = ray_r >= lam0
+    ups = sim.updates_per_step
+    return dict(
+        lattice="D2Q9", levels=levels, shapes=[list(s[:2]) for s in shapes],
+        boxes=[[list(lo[:2]), list(hi[:2])] for lo, hi in boxes], D_finest=D, D_level0=D0,
+        ma=ma, re=re, tau=[round(t, 6) for t in _taus(tau0, levels)],
+        storage=storage, layer_D=list(layer_D), chi_max=chi_max, coarse_steps=coarse_steps,
+        window_coarse_steps=window,
+        st=None if st is None else round(st, 4),
+        st_spectrum=round(A.peak_frequency(cl_w, fine_dt) * D / U, 4),
+        cl_amplitude=round(A.amplitude(cl_w), 4),
+        cl_rms_sqrt2=round(float(cl_w.std() * math.sqrt(2)), 4),
+        cd_mean=round(float(cd_w.mean()), 4),
+        prms_peak_angle_from_downstream_deg=round(A.directivity_peak(rms[ring], ring_angles), 2),
+        prms_ring_D=ring_D,
+        wavelength_D=round(lam0 / D0, 2),
+        wave_ray_radii_D=[round(float(r) / D0, 2) for r in ray_r],
+        wave_ray_amplitude=[float("%.4g" % v) for v in amp],
+        wave_decay_exponent=round(A.decay_exponent(ray_r, amp), 3),
+        wave_decay_exponent_beyond_one_wavelength=(
+            round(A.decay_exponent(ray_r[far], amp[far]), 3) if far.sum() >= 3 else None),
+        updates_per_coarse_step=ups,
+        mlups=round(ups * coarse_steps / elapsed / 1e6, 1), seconds=round(elapsed, 2))
+
+
+def _taus(tau0, levels):
+    t = [tau0]
+    for _ in range(levels - 1):
+        t.append(2.0 * t[-1] - 0.5)
+    return t
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--D", type=int, default=32, help="cells per diameter on the finest level")
+    ap.add_argument("--extent", type=float, default=160.0, help="level-0 side in diameters")
+    ap.add_argument("--coarse-steps", type=int, default=8000)
+    ap.add_argument("--window", type=int, default=4000, help="analysed coarse steps")
+    ap.add_argument("--storage", default="f32")
+    args = ap.parse_args(argv)
+    hw = (24.0, 10.0, 4.0, 2.0)[: args.levels - 1]
+    res = run(levels=args.levels, D=args.D, extent=args.extent, halfwidths=hw,
+              coarse_steps=args.coarse_steps, window=args.window, storage=args.storage,
+              log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

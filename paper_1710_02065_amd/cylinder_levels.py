@@ -55,6 +55,26 @@ def geometry(levels, D, extent, halfwidths, downstream):
     return n0, D0, boxes, centres
 
 
+def locate(points, boxes, shapes, margin=3):
+    """For points (x, y) in level-0 coordinates, the finest level whose grid
+    holds each point at least `margin` nodes inside its box (coarser levels
+    do not update the nodes a finer level covers), and the cell index on
+    that level.  Returns (levels [n], cells [n])."""
+    lev, cells = [], []
+    for x, y in points:
+        best = (0, int(round(y)) * shapes[0][0] + int(round(x)))
+        px, py = float(x), float(y)
+        for l, (lo, hi) in enumerate(boxes):
+            px, py = 2.0 * (px - lo[0]), 2.0 * (py - lo[1])
+            nx, ny = shapes[l + 1][0], shapes[l + 1][1]
+            if not (margin <= px <= nx - 1 - margin and margin <= py <= ny - 1 - margin):
+                break
+            best = (l + 1, int(round(py)) * nx + int(round(px)))
+        lev.append(best[0])
+        cells.append(best[1])
+    return np.array(lev), np.array(cells, dtype=np.int64)
+
+
 def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1.5,
         ma=0.2, re=150.0, coarse_steps=8000, window=4000, layer_D=(50.0, 115.0),
         chi_max=0.5, face_layer_D=20.0, face_chi=0.3, storage="f32", seed=2,
@@ -98,23 +118,35 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
         layers.face_layer((n0, n0, 1), (int(face_layer_D * D0),) * 4 + (0, 0), face_chi))
     sim.set_sponge(chi, level=0)
 
+    # probes on the finest level that holds each point (level-0 cells
+    # inside a refined box are covered and not updated)
     ring_angles = np.arange(30.0, 150.1, 1.0)
-    ring = A.ring_cells(n0, n0, cx0, cy0, ring_D * D0, ring_angles)
+    th = np.radians(ring_angles)
+    ring_lev, ring_cell = locate(np.stack([cx0 + ring_D * D0 * np.cos(th),
+                                           cy0 + ring_D * D0 * np.sin(th)], 1), boxes, shapes)
     clear = layer_D[0] * D0
     ray_r = np.geomspace(2.0 * D0, 0.95 * clear, 32)
-    ray = torch.tensor((cy0 + np.round(ray_r).astype(np.int64)) * n0 + cx0, device=dev)
+    ray_lev, ray_cell = locate(np.stack([np.full_like(ray_r, cx0), cy0 + ray_r], 1), boxes,
+                               shapes)
+    ray_sets = [(l, np.nonzero(ray_lev == l)[0]) for l in range(levels) if (ray_lev == l).any()]
+    ray_dev = [(l, torch.tensor(k, device=dev), torch.tensor(ray_cell[k], device=dev))
+               for l, k in ray_sets]
     forces = torch.zeros(coarse_steps, 3, dtype=torch.float64, device=dev)
-    probes = torch.zeros(window, len(ray), dtype=torch.float64, device=dev)
-    s1 = torch.zeros(n0 * n0, dtype=torch.float64, device=dev)
-    s2 = torch.zeros_like(s1)
+    probes = torch.zeros(window, len(ray_r), dtype=torch.float64, device=dev)
+    acc_levels = sorted(set(ring_lev.tolist()))
+    sums = {l: (torch.zeros(shapes[l][0] * shapes[l][1], dtype=torch.float64, device=dev),
+                torch.zeros(shapes[l][0] * shapes[l][1], dtype=torch.float64, device=dev))
+            for l in acc_levels}
     t0 = time.time()
     w0 = coarse_steps - window
     for s in range(coarse_steps):
         sim.step(1)
         sim.force(level=levels - 1, out=forces[s])
         if s >= w0:
-            lbm.lbm_probe(sim.ctx, 0, ray, probes[s - w0])
-            sim.accumulate(s1, s2, level=0)
+            for l, k, cells in ray_dev:
+                probes[s - w0, k] = sim.probe(cells, level=l)
+            for l, (a1, a2) in sums.items():
+                sim.accumulate(a1, a2, level=l)
         if log and s % 1000 == 999:
             log("cylinder levels %d/%d coarse steps %.1fs" % (s + 1, coarse_steps,
                                                               time.time() - t0))
@@ -126,7 +158,11 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
     # times in fine-level steps: one sample per coarse step
     st = A.strouhal(cl_w, D, U, dt=fine_dt)
     f_shed = (st if st else A.peak_frequency(cl_w, fine_dt) * D / U) * U / D
-    rms = A.rms_from_sums(s1.cpu().numpy(), s2.cpu().numpy(), window) * CS * CS
+    rms_ring = np.zeros(len(ring_angles))
+    for l, (a1, a2) in sums.items():
+        k = ring_lev == l
+        r = A.rms_from_sums(a1.cpu().numpy(), a2.cpu().numpy(), window) * CS * CS
+        rms_ring[k] = r[ring_cell[k]]
     p = probes.cpu().numpy() * CS * CS
     # level-0 samples are one coarse step apart; the tone's frequency there
     # is f_shed per fine step times fine_dt
@@ -145,8 +181,9 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
         cl_amplitude=round(A.amplitude(cl_w), 4),
         cl_rms_sqrt2=round(float(cl_w.std() * math.sqrt(2)), 4),
         cd_mean=round(float(cd_w.mean()), 4),
-        prms_peak_angle_from_downstream_deg=round(A.directivity_peak(rms[ring], ring_angles), 2),
-        prms_ring_D=ring_D,
+        prms_peak_angle_from_downstream_deg=round(A.directivity_peak(rms_ring, ring_angles), 2),
+        prms_ring_D=ring_D, prms_ring_levels=sorted(set(ring_lev.tolist())),
+        ray_levels=[int(v) for v in ray_lev],
         wavelength_D=round(lam0 / D0, 2),
         wave_ray_radii_D=[round(float(r) / D0, 2) for r in ray_r],
         wave_ray_amplitude=[float("%.4g" % v) for v in amp],

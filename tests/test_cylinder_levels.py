@@ -36,3 +36,22 @@ def test_relaxation_times_follow_the_interface_rule():
     t = C._taus(0.51, 4)
     for a, b in zip(t, t[1:]):
         assert abs(b - (2 * a - 0.5)) < 1e-15
+
+
+def test_locate_maps_points_to_the_finest_level_holding_them():
+    import numpy as np
+    n0, D0, boxes, centres = C.geometry(4, 32, 160.0, (24.0, 10.0, 4.0), 1.5)
+    shapes = [(n0, n0)]
+    for lo, hi in boxes:
+        shapes.append((2 * (hi[0] - lo[0]) + 1, 2 * (hi[1] - lo[1]) + 1))
+    c = centres[0]
+    r = np.geomspace(2.0 * D0, 45.0 * D0, 20)
+    lev, cells = C.locate(np.stack([np.full_like(r, c[0]), c[1] + r], 1), boxes, shapes)
+    assert lev[0] == 3 and lev[-1] == 0 and np.all(np.diff(lev) <= 0)
+    for l, cell, rr in zip(lev, cells, r):
+        nx = shapes[l][0]
+        x, y = float(cell % nx), float(cell // nx)
+        for k in range(l, 0, -1):
+            lo = boxes[k - 1][0]
+            x, y = x / 2 + lo[0], y / 2 + lo[1]
+        assert abs(x - c[0]) <= 0.5 and abs(y - (c[1] + rr)) <= 0.5

@@ -169,6 +169,19 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
     amp = np.array([A.tone_amplitude(p[:, j], f_shed * fine_dt, 1.0) for j in range(p.shape[1])])
     lam0 = CS / (f_shed * fine_dt)          # acoustic wavelength in level-0 cells
     far = ray_r >= lam0
+    # overall level at one wavelength, extrapolated to the farthest ray
+    # point with 2D (cylindrical) spreading, against the level measured there
+    p_ref = 1e-6
+    i1 = int(np.argmax(far))
+    i2 = len(ray_r) - 1
+    L1, L2 = A.oaspl(p[:, i1], p_ref), A.oaspl(p[:, i2], p_ref)
+    L2x = float(A.extrapolate_level(L1, ray_r[i1], ray_r[i2], spreading="cylindrical"))
+    # one-third-octave levels at the farthest point (frequencies per level-0
+    # step); the band holding the shedding tone should dominate
+    fc, flo, fhi = A.third_octave_bands(0.1 * f_shed * fine_dt, 8.0 * f_shed * fine_dt,
+                                        f_ref=f_shed * fine_dt)
+    bands = A.band_levels(p[:, i2], 1.0, fc, flo, fhi, p_ref)
+    k = int(np.argmax(bands))
     ups = sim.updates_per_step
     return dict(
         lattice="D2Q9", levels=levels, shapes=[list(s[:2]) for s in shapes],
@@ -187,6 +200,12 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
         wavelength_D=round(lam0 / D0, 2),
         wave_ray_radii_D=[round(float(r) / D0, 2) for r in ray_r],
         wave_ray_amplitude=[float("%.4g" % v) for v in amp],
+        oaspl_db=dict(r1_D=round(float(ray_r[i1]) / D0, 2), at_r1=round(L1, 2),
+                      r2_D=round(float(ray_r[i2]) / D0, 2), at_r2=round(L2, 2),
+                      r2_from_r1_cylindrical=round(L2x, 2), p_ref=p_ref),
+        third_octave_peak=dict(band_centre_over_f_shed=round(float(fc[k] / (f_shed * fine_dt)), 4),
+                               level_db=round(float(bands[k]), 2),
+                               next_highest_db=round(float(np.sort(bands)[-2]), 2)),
         wave_decay_exponent=round(A.decay_exponent(ray_r, amp), 3),
         wave_decay_exponent_beyond_one_wavelength=(
             round(A.decay_exponent(ray_r[far], amp[far]), 3) if far.sum() >= 3 else None),

@@ -20,8 +20,8 @@
  *  - eq. (neqH): no rho factor; a2_neq is an absolute moment.
  *  - a2 = Pi - rho*cs^2*I (the printed "a2 = P - rho(uu - delta)" is garbled);
  *    a2_neq = Pi - rho*cs^2*I - rho*u*u.
- *  - third-order basis per lattice (Sec. II.A, "special property" of D2Q9 and
- *    D3Q27): D2Q9 {xxy, xyy}; D3Q27 {xxy, xyy, xxz, xzz, yyz, yzz, xyz};
+ *  - third-order basis per lattice (Sec. II.A singles out D2Q9 and D3Q27
+ *    for it): D2Q9 {xxy, xyy}; D3Q27 {xxy, xyy, xxz, xzz, yyz, yzz, xyz};
  *    D3Q19 (not covered by that property) uses the lattice-orthogonal
  *    combinations (H_xxy +- H_yzz) and likewise for the x- and z-odd pairs.
  *    Each basis element k is rebuilt as w_i H_k,i c_k / N_k, with N_k the
@@ -199,7 +199,7 @@ static double ora_third_order(const ora_lattice* L, int i, double a3[3][3][3]) {
 
 /* ------------------------------------------------------------------------ */
 /* Full recursive regularization (Sec. II.A, expansion to order n > 2 on the */
-/* lattices with the "special property", D2Q9 and D3Q27).  These are tensor  */
+/* lattices Sec. II.A singles out, D2Q9 and D3Q27).  These are tensor       */
 /* products of the 1D three-velocity quadrature, on which the 1D Hermite     */
 /* polynomial of degree 3 vanishes (xi^3 = xi and 3 cs^2 = 1); the Hermite   */
 /* polynomials they resolve are the products He_nx(xi_x) He_ny(xi_y)        */

@@ -171,133 +171,138 @@ def time_steps(sim, torch, steps):
     return a.elapsed_time(b)
 
 
-def other_configs(lbm, torch, steps, shedding_steps):
+def other_configs(lbm, torch, steps, shedding_steps, which=("c1", "c2", "stability", "c4")):
     """Full-size runs of the other single-GPU configurations (not the
-    headline): the D2Q9 cylinder channel and the D3Q27 jet with a 2:1 block."""
+    headline): the D2Q9 Taylor-Green and cylinder channel, the stability
+    study and the D3Q27 jet with a 2:1 block; `which` selects them."""
     from paper_1710_02065_amd import workloads as W
     res = {}
-    # D2Q9 128^2 periodic Taylor-Green in FP64 (U = 0.05, tau 0.6, 1000
-    # steps): fitted viscosity against cs^2 (tau - 1/2) = 1/30, mass and
-    # momentum drift; a latency-bound size, timed for completeness
-    n1, U1, tau1, T1 = 128, 0.05, 0.6, 1000
-    rho1, u1, S1 = W.taylor_green_2d(n1, U1)
-    sim = lbm.Simulation(lattice=9, shape=(n1, n1, 1), tau=tau1, storage="f64")
-    sim.init(rho1, u1, -2.0 * rho1 * tau1 / 3.0 * S1)
-    mode = torch.from_numpy(W.taylor_green_mode_2d(n1)).cuda()
-    t0 = sim.totals().cpu().numpy()
-    sim.step(100)
-    a0 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
-    ms1 = time_steps(sim, torch, T1 - 100)
-    a1 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
-    t1 = sim.totals().cpu().numpy()
-    sim.sync()
-    k1 = 2 * math.pi / n1
-    nu_fit = -math.log(a1 / a0) / (2 * k1 * k1 * (T1 - 100))
-    res["d2q9_taylor_green_128_f64"] = dict(
-        nu_fit=nu_fit, nu_theory=1.0 / 30.0, nu_rel_error=nu_fit * 30.0 - 1.0,
-        mass_drift=float(abs(t1[0] - t0[0]) / (n1 * n1)),
-        momentum_drift=float(np.abs(t1[1:] - t0[1:]).max() / (n1 * n1)),
-        mlups=round(n1 * n1 * (T1 - 100) / (ms1 * 1e3), 1), steps=T1,
-        note="drifts per cell; 16k cells cannot fill the GPU")
-    del sim
-    # D2Q9 2048 x 1024 channel, cylinder D = 100 at (400, 512), Ma 0.2, Re 150
-    nx, ny, D = 2048, 1024, 100
-    U = 0.2 * math.sqrt(1.0 / 3.0)
-    sim = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150, storage="f32",
-                         ma=0.2, face_bc=(2, 2, 1, 1, 0, 0), sponge_width=(0, 128, 0, 0, 0, 0),
-                         chi_max=0.2, rho_ref=1.0, u_ref=(U, 0, 0), seed=2)
-    rho, u = W.uniform_perturbed((nx, ny, 1), U, (1, 0, 0), seed=2, rel_noise=1e-4, d=2)
-    sim.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
-    sim.step(64)
-    sim.block = lbm.lbm_autotune(sim.ctx, 2)
-    ms = time_steps(sim, torch, steps)
-    N = nx * ny
-    bytes_lup = 2 * 9 * 4 + 1
-    res["d2q9_cylinder_2048x1024_f32"] = dict(
-        mlups=round(N * steps / (ms * 1e3), 1), steps=steps, workgroup=sim.block,
-        hbm_gbs=round(bytes_lup * N * steps / (ms / 1e3) / 1e9, 1),
-        note="72 B/LUP populations + 1 B mask; 151 MB of state fits the 256 MB MALL")
-    del sim
-    torch.cuda.empty_cache()
-    # the channel in FP32 against the FP64 build (equal to the oracle within
-    # 1e-12 in the parity tests) after 2000 steps
-    fields = {}
-    for st in ("f64", "f32"):
-        sv = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150,
-                            storage=st, ma=0.2, face_bc=(2, 2, 1, 1, 0, 0),
-                            sponge_width=(0, 128, 0, 0, 0, 0), chi_max=0.2, rho_ref=1.0,
-                            u_ref=(U, 0, 0), seed=2)
-        sv.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
-        sv.step(2000)
-        fields[st] = sv.moments()
-        sv.sync()
-        del sv
-    (r64, u64), (r32, u32) = fields["f64"], fields["f32"]
-    fluid = r64 != 0
-    p64 = (r64 - 1.0)[fluid]
-    res["d2q9_cylinder_2048x1024_f32_vs_f64_2000_steps"] = dict(
-        p_rel_l2=float(((r32 - r64)[fluid]).norm() / p64.norm()),
-        u_rel_l2=float((u32 - u64)[:, fluid].norm() / u64[:, fluid].norm()),
-        u_max_abs=float((u32 - u64)[:, fluid].abs().max()))
-    del fields, r64, u64, r32, u32
-    torch.cuda.empty_cache()
-    if shedding_steps:
-        # the same channel run long enough for periodic shedding: C_L, St
-        # and C_D by momentum exchange (Sec. III); walls 5 D from the body
-        from paper_1710_02065_amd import cylinder_study
-        w = min(60000, shedding_steps // 2)
-        res["d2q9_cylinder_2048x1024_shedding"] = cylinder_study.run(
-            steps=shedding_steps, window=w, acoustics=False,
-            probe_cells=W.cylinder_probes(nx, ny, D, 400, 512), log=log)
-        res["d2q9_cylinder_2048x1024_shedding"]["probes"] = (
-            "p = cs^2 rho every 10 steps at r = 1.5, 2, 3, 4 D along 90 and 78.2 degrees")
-        torch.cuda.empty_cache()
-    # stability of the collision operators (Sec. II.A): smallest stable tau
-    # on a D2Q9 128^2 thick shear layer at Ma 0.2
-    from paper_1710_02065_amd import stability_study
-    res["d2q9_shear_layer_stability"] = stability_study.run(n=128, ma=0.2, log=log)
-    torch.cuda.empty_cache()
-    # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
-    # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]
-    # The second run gives the outflow layer the round-jet similarity field
-    # as its reference (Sec. IV), through the per-cell layer with the same
-    # face profile.
-    from paper_1710_02065_amd import layers
-    shape = (384, 256, 256)
-    Uj = 0.3 * math.sqrt(1.0 / 3.0)
-    nu = Uj * 20 / 3600
-    tau = 0.5 + 3 * nu
-    lo, hi = (4, 64, 64), (196, 191, 191)
-    widths = (0, 64, 64, 64, 64, 64)
-    for name, field in (("d3q27_jet_384x256x256_refined_f32", False),
-                        ("d3q27_jet_384x256x256_refined_f32_similarity_reference", True)):
-        sim = lbm.Simulation(lattice=27, shape=shape, tau=tau, storage="f32", ma=0.3,
-                             face_bc=(2, 2, 2, 2, 2, 2), sponge_width=widths,
-                             chi_max=0.2, rho_ref=1.0, seed=4, inlet_noise=0.02,
-                             refine_lo=lo, refine_hi=hi,
-                             flags=lbm.LBM_SPONGE_FIELD if field else 0)
-        sim.init(None, torch.zeros(3, shape[0] * shape[1] * shape[2], dtype=torch.float64,
-                                   device="cuda"), None, W.jet_inlet_mask(*shape, D=20), level=0)
-        fs = sim.shape(1)
-        sim.init(None, torch.zeros(3, fs[0] * fs[1] * fs[2], dtype=torch.float64,
-                                   device="cuda"), level=1)
-        if field:
-            rr, ur = layers.jet_reference(shape, 20.0, Uj)
-            sim.set_sponge(layers.face_layer(shape, widths, 0.2), rr, ur, level=0)
-            del rr, ur
-        sim.step(8)
-        js = max(steps // 10, 20)
-        ms = time_steps(sim, torch, js)
-        ups = sim.updates_per_step
-        res[name] = dict(
-            mlups=round(ups * js / (ms * 1e3), 1), coarse_steps=js, updates_per_coarse_step=ups,
-            hbm_gbs=round(2 * 27 * 4 * ups * js / (ms / 1e3) / 1e9, 1),
-            note="updates = swept coarse cells + 2 x swept fine cells per coarse step; "
-                 "refined block starts 4 cells from the inlet face (coupling margin)"
-                 + ("; per-cell layer (20 B more per layer cell) with the round-jet "
-                    "similarity velocity as reference" if field else ""))
+    if "c1" in which:
+        # D2Q9 128^2 periodic Taylor-Green in FP64 (U = 0.05, tau 0.6, 1000
+        # steps): fitted viscosity against cs^2 (tau - 1/2) = 1/30, mass and
+        # momentum drift; a latency-bound size, timed for completeness
+        n1, U1, tau1, T1 = 128, 0.05, 0.6, 1000
+        rho1, u1, S1 = W.taylor_green_2d(n1, U1)
+        sim = lbm.Simulation(lattice=9, shape=(n1, n1, 1), tau=tau1, storage="f64")
+        sim.init(rho1, u1, -2.0 * rho1 * tau1 / 3.0 * S1)
+        mode = torch.from_numpy(W.taylor_green_mode_2d(n1)).cuda()
+        t0 = sim.totals().cpu().numpy()
+        sim.step(100)
+        a0 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
+        ms1 = time_steps(sim, torch, T1 - 100)
+        a1 = float((sim.moments()[1][0] @ mode) / (mode @ mode))
+        t1 = sim.totals().cpu().numpy()
+        sim.sync()
+        k1 = 2 * math.pi / n1
+        nu_fit = -math.log(a1 / a0) / (2 * k1 * k1 * (T1 - 100))
+        res["d2q9_taylor_green_128_f64"] = dict(
+            nu_fit=nu_fit, nu_theory=1.0 / 30.0, nu_rel_error=nu_fit * 30.0 - 1.0,
+            mass_drift=float(abs(t1[0] - t0[0]) / (n1 * n1)),
+            momentum_drift=float(np.abs(t1[1:] - t0[1:]).max() / (n1 * n1)),
+            mlups=round(n1 * n1 * (T1 - 100) / (ms1 * 1e3), 1), steps=T1,
+            note="drifts per cell; 16k cells cannot fill the GPU")
+        del sim
+    if "c2" in which:
+        # D2Q9 2048 x 1024 channel, cylinder D = 100 at (400, 512), Ma 0.2, Re 150
+        nx, ny, D = 2048, 1024, 100
+        U = 0.2 * math.sqrt(1.0 / 3.0)
+        sim = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150, storage="f32",
+                             ma=0.2, face_bc=(2, 2, 1, 1, 0, 0), sponge_width=(0, 128, 0, 0, 0, 0),
+                             chi_max=0.2, rho_ref=1.0, u_ref=(U, 0, 0), seed=2)
+        rho, u = W.uniform_perturbed((nx, ny, 1), U, (1, 0, 0), seed=2, rel_noise=1e-4, d=2)
+        sim.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
+        sim.step(64)
+        sim.block = lbm.lbm_autotune(sim.ctx, 2)
+        ms = time_steps(sim, torch, steps)
+        N = nx * ny
+        bytes_lup = 2 * 9 * 4 + 1
+        res["d2q9_cylinder_2048x1024_f32"] = dict(
+            mlups=round(N * steps / (ms * 1e3), 1), steps=steps, workgroup=sim.block,
+            hbm_gbs=round(bytes_lup * N * steps / (ms / 1e3) / 1e9, 1),
+            note="72 B/LUP populations + 1 B mask; 151 MB of state fits the 256 MB MALL")
         del sim
         torch.cuda.empty_cache()
+        # the channel in FP32 against the FP64 build (equal to the oracle within
+        # 1e-12 in the parity tests) after 2000 steps
+        fields = {}
+        for st in ("f64", "f32"):
+            sv = lbm.Simulation(lattice=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150,
+                                storage=st, ma=0.2, face_bc=(2, 2, 1, 1, 0, 0),
+                                sponge_width=(0, 128, 0, 0, 0, 0), chi_max=0.2, rho_ref=1.0,
+                                u_ref=(U, 0, 0), seed=2)
+            sv.init(rho, u, None, W.cylinder_mask(nx, ny, D, 400, 512))
+            sv.step(2000)
+            fields[st] = sv.moments()
+            sv.sync()
+            del sv
+        (r64, u64), (r32, u32) = fields["f64"], fields["f32"]
+        fluid = r64 != 0
+        p64 = (r64 - 1.0)[fluid]
+        res["d2q9_cylinder_2048x1024_f32_vs_f64_2000_steps"] = dict(
+            p_rel_l2=float(((r32 - r64)[fluid]).norm() / p64.norm()),
+            u_rel_l2=float((u32 - u64)[:, fluid].norm() / u64[:, fluid].norm()),
+            u_max_abs=float((u32 - u64)[:, fluid].abs().max()))
+        del fields, r64, u64, r32, u32
+        torch.cuda.empty_cache()
+        if shedding_steps:
+            # the same channel run long enough for periodic shedding: C_L, St
+            # and C_D by momentum exchange (Sec. III); walls 5 D from the body
+            from paper_1710_02065_amd import cylinder_study
+            w = min(60000, shedding_steps // 2)
+            res["d2q9_cylinder_2048x1024_shedding"] = cylinder_study.run(
+                steps=shedding_steps, window=w, acoustics=False,
+                probe_cells=W.cylinder_probes(nx, ny, D, 400, 512), log=log)
+            res["d2q9_cylinder_2048x1024_shedding"]["probes"] = (
+                "p = cs^2 rho every 10 steps at r = 1.5, 2, 3, 4 D along 90 and 78.2 degrees")
+            torch.cuda.empty_cache()
+    if "stability" in which:
+        # stability of the collision operators (Sec. II.A): smallest stable tau
+        # on a D2Q9 128^2 thick shear layer at Ma 0.2
+        from paper_1710_02065_amd import stability_study
+        res["d2q9_shear_layer_stability"] = stability_study.run(n=128, ma=0.2, log=log)
+        torch.cuda.empty_cache()
+    if "c4" in which:
+        # D3Q27 384 x 256 x 256 jet, inlet disc D = 20 at Ma 0.3 with 2 % noise,
+        # Re 3600, 64-cell sponge on x+, y+-, z+-, 2:1 block [4,196]x[64,191]x[64,191]
+        # The second run gives the outflow layer the round-jet similarity field
+        # as its reference (Sec. IV), through the per-cell layer with the same
+        # face profile.
+        from paper_1710_02065_amd import layers
+        shape = (384, 256, 256)
+        Uj = 0.3 * math.sqrt(1.0 / 3.0)
+        nu = Uj * 20 / 3600
+        tau = 0.5 + 3 * nu
+        lo, hi = (4, 64, 64), (196, 191, 191)
+        widths = (0, 64, 64, 64, 64, 64)
+        for name, field in (("d3q27_jet_384x256x256_refined_f32", False),
+                            ("d3q27_jet_384x256x256_refined_f32_similarity_reference", True)):
+            sim = lbm.Simulation(lattice=27, shape=shape, tau=tau, storage="f32", ma=0.3,
+                                 face_bc=(2, 2, 2, 2, 2, 2), sponge_width=widths,
+                                 chi_max=0.2, rho_ref=1.0, seed=4, inlet_noise=0.02,
+                                 refine_lo=lo, refine_hi=hi,
+                                 flags=lbm.LBM_SPONGE_FIELD if field else 0)
+            sim.init(None, torch.zeros(3, shape[0] * shape[1] * shape[2], dtype=torch.float64,
+                                       device="cuda"), None, W.jet_inlet_mask(*shape, D=20), level=0)
+            fs = sim.shape(1)
+            sim.init(None, torch.zeros(3, fs[0] * fs[1] * fs[2], dtype=torch.float64,
+                                       device="cuda"), level=1)
+            if field:
+                rr, ur = layers.jet_reference(shape, 20.0, Uj)
+                sim.set_sponge(layers.face_layer(shape, widths, 0.2), rr, ur, level=0)
+                del rr, ur
+            sim.step(8)
+            js = max(steps // 10, 20)
+            ms = time_steps(sim, torch, js)
+            ups = sim.updates_per_step
+            res[name] = dict(
+                mlups=round(ups * js / (ms * 1e3), 1), coarse_steps=js, updates_per_coarse_step=ups,
+                hbm_gbs=round(2 * 27 * 4 * ups * js / (ms / 1e3) / 1e9, 1),
+                note="updates = swept coarse cells + 2 x swept fine cells per coarse step; "
+                     "refined block starts 4 cells from the inlet face (coupling margin)"
+                     + ("; per-cell layer (20 B more per layer cell) with the round-jet "
+                        "similarity velocity as reference" if field else ""))
+            del sim
+            torch.cuda.empty_cache()
     return res
 
 
@@ -351,6 +356,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--config-steps", type=int, default=500)
+    ap.add_argument("--configs", default="c1,c2,stability,c4",
+                    help="comma-separated subset of the other configurations to run")
     ap.add_argument("--shedding-steps", type=int, default=160000,
                     help="cylinder channel steps for C_L / St (0: skip)")
     ap.add_argument("--precision-horizons", type=lambda s: [int(x) for x in s.split(",")],
@@ -478,7 +485,8 @@ def main():
     out["config"]["workgroup"] = wg32
     if not args.no_configs:
         log("other configurations")
-        out["configs"] = other_configs(lbm, torch, args.config_steps, args.shedding_steps)
+        out["configs"] = other_configs(lbm, torch, args.config_steps, args.shedding_steps,
+                                       which=tuple(args.configs.split(",")))
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving: %d jobs, step scale %g" % (args.serve_jobs, args.serve_step_scale))

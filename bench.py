@@ -171,10 +171,12 @@ def time_steps(sim, torch, steps):
     return a.elapsed_time(b)
 
 
-def other_configs(lbm, torch, steps, shedding_steps, which=("c1", "c2", "stability", "c4")):
+def other_configs(lbm, torch, steps, shedding_steps,
+                  which=("c1", "c2", "cylinder_levels", "stability", "c4")):
     """Full-size runs of the other single-GPU configurations (not the
-    headline): the D2Q9 Taylor-Green and cylinder channel, the stability
-    study and the D3Q27 jet with a 2:1 block; `which` selects them."""
+    headline): the D2Q9 Taylor-Green and cylinder channel, the cylinder on
+    four nested levels, the stability study and the D3Q27 jet with a 2:1
+    block; `which` selects them."""
     from paper_1710_02065_amd import workloads as W
     res = {}
     if "c1" in which:
@@ -255,6 +257,12 @@ def other_configs(lbm, torch, steps, shedding_steps, which=("c1", "c2", "stabili
             res["d2q9_cylinder_2048x1024_shedding"]["probes"] = (
                 "p = cs^2 rho every 10 steps at r = 1.5, 2, 3, 4 D along 90 and 78.2 degrees")
             torch.cuda.empty_cache()
+    if "cylinder_levels" in which:
+        # the cylinder on four nested levels with a circular layer (the
+        # arrangement of Sec. III): C_L, St, C_D, directivity, far-field decay
+        from paper_1710_02065_amd import cylinder_levels
+        res["d2q9_cylinder_four_levels"] = cylinder_levels.run(log=log)
+        torch.cuda.empty_cache()
     if "stability" in which:
         # stability of the collision operators (Sec. II.A): smallest stable tau
         # on a D2Q9 128^2 thick shear layer at Ma 0.2
@@ -356,7 +364,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--config-steps", type=int, default=500)
-    ap.add_argument("--configs", default="c1,c2,stability,c4",
+    ap.add_argument("--configs", default="c1,c2,cylinder_levels,stability,c4",
                     help="comma-separated subset of the other configurations to run")
     ap.add_argument("--shedding-steps", type=int, default=160000,
                     help="cylinder channel steps for C_L / St (0: skip)")

@@ -357,6 +357,10 @@ static int advance(lbm_ctx* ctx, int l, bool record_band, hipStream_t st) {
   return LBM_OK;
 }
 
+int refined_record_parity(const lbm_ctx* ctx, int l) { return ctx->ref[l]->prev; }
+
+void set_refined_record_parity(lbm_ctx* ctx, int l, int parity) { ctx->ref[l]->prev = parity; }
+
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st) {
   int rc = advance(ctx, 0, false, st);
   if (rc != LBM_OK) return rc;

@@ -432,11 +432,70 @@ static void drop_graphs(lbm_ctx* ctx) {
 
 static bool graphs_allowed(const lbm_ctx* ctx) {
   if (ctx->cfg.flags & LBM_NO_GRAPH) return false;
-  // time-dependent kernel arguments (inlet noise, refinement schedule
-  // parities) would be frozen into the graph
+  // inlet noise depends on the absolute time, which a graph would freeze
   if (ctx->has_inlet && ctx->cfg.inlet_noise != 0.0) return false;
-  if (ctx->nlevels > 1) return false;
   return true;
+}
+
+// Refined contexts replay graphs of two coarse steps: level 0's buffer and
+// the level-0 record parity flip once per coarse step and every finer level
+// advances an even number of times, so after two coarse steps the whole
+// schedule is back in the state it was captured from.
+static constexpr int64_t kRefinedGraphSteps = 2;
+
+static int step_graph_refined(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
+  const int key = 2 + ctx->lv[0].cur;  // keys 0 / 1 are the single-level graphs
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (!ctx->capture_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_error(e, "hipStreamCreate");
+    }
+    // the capture runs the host side of the schedule without executing it:
+    // keep its state and put it back afterwards
+    int cur[kMaxLevels], prev[kMaxLevels];
+    int64_t t[kMaxLevels];
+    const int64_t t_ctx = ctx->t;
+    for (int l = 0; l < ctx->nlevels; ++l) {
+      cur[l] = ctx->lv[l].cur;
+      t[l] = ctx->lv[l].t;
+      prev[l] = l + 1 < ctx->nlevels ? refined_record_parity(ctx, l) : 0;
+    }
+    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    int rc = LBM_OK;
+    for (int64_t s = 0; s < kRefinedGraphSteps && rc == LBM_OK; ++s)
+      rc = refined_coarse_step(ctx, ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
+    for (int l = 0; l < ctx->nlevels; ++l) {
+      ctx->lv[l].cur = cur[l];
+      ctx->lv[l].t = t[l];
+      if (l + 1 < ctx->nlevels) set_refined_record_parity(ctx, l, prev[l]);
+    }
+    ctx->t = t_ctx;
+    if (rc != LBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e2 != hipSuccess) return hip_error(e2, "hipStreamEndCapture");
+    GraphEntry g{};
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_error(e, "hipGraphInstantiate");
+    }
+    it = ctx->graphs.emplace(key, g).first;
+  }
+  for (int64_t k = 0; k < chunks; ++k) {
+    hipError_t e = hipGraphLaunch(it->second.exec, st);
+    if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  }
+  // even number of coarse steps: every parity is unchanged
+  for (int l = 0; l < ctx->nlevels; ++l) ctx->lv[l].t += (chunks * kRefinedGraphSteps) << l;
+  ctx->t += chunks * kRefinedGraphSteps;
+  return LBM_OK;
 }
 
 static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
@@ -482,7 +541,12 @@ static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
 
 int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st) {
   if (n < 0) return set_error(LBM_EINVAL, "negative step count");
-  if (graphs_allowed(ctx) && n >= 2 * kGraphSteps) {
+  if (graphs_allowed(ctx) && ctx->nlevels > 1 && n >= kRefinedGraphSteps) {
+    const int64_t chunks = n / kRefinedGraphSteps;
+    int rc = step_graph_refined(ctx, chunks, st);
+    if (rc != LBM_OK) return rc;
+    n -= chunks * kRefinedGraphSteps;
+  } else if (graphs_allowed(ctx) && ctx->nlevels == 1 && n >= 2 * kGraphSteps) {
     const int64_t chunks = n / kGraphSteps;
     int rc = step_graph(ctx, chunks, st);
     if (rc != LBM_OK) return rc;

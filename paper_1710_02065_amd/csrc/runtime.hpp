@@ -116,6 +116,9 @@ int refined_after_init(lbm_ctx* ctx);
 int64_t refined_updates_per_step(const lbm_ctx* ctx);
 int refined_after_set(lbm_ctx* ctx, int level);
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st);
+// which of the two parent-side records of interface l holds M_l(t)
+int refined_record_parity(const lbm_ctx* ctx, int l);
+void set_refined_record_parity(lbm_ctx* ctx, int l, int parity);
 int make_levels_refined(lbm_ctx* ctx);
 void free_refinement(lbm_ctx* ctx);
 

@@ -131,42 +131,46 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
     ray_sets = [(l, np.nonzero(ray_lev == l)[0]) for l in range(levels) if (ray_lev == l).any()]
     ray_dev = [(l, torch.tensor(k, device=dev), torch.tensor(ray_cell[k], device=dev))
                for l, k in ray_sets]
-    forces = torch.zeros(coarse_steps, 3, dtype=torch.float64, device=dev)
-    probes = torch.zeros(window, len(ray_r), dtype=torch.float64, device=dev)
+    # one sample every two coarse steps (the refined schedule replays as a
+    # captured graph of two coarse steps)
+    every = 2
+    nsamp, wsamp = coarse_steps // every, window // every
+    forces = torch.zeros(nsamp, 3, dtype=torch.float64, device=dev)
+    probes = torch.zeros(wsamp, len(ray_r), dtype=torch.float64, device=dev)
     acc_levels = sorted(set(ring_lev.tolist()))
     sums = {l: (torch.zeros(shapes[l][0] * shapes[l][1], dtype=torch.float64, device=dev),
                 torch.zeros(shapes[l][0] * shapes[l][1], dtype=torch.float64, device=dev))
             for l in acc_levels}
     t0 = time.time()
-    w0 = coarse_steps - window
-    for s in range(coarse_steps):
-        sim.step(1)
+    w0 = nsamp - wsamp
+    for s in range(nsamp):
+        sim.step(every)
         sim.force(level=levels - 1, out=forces[s])
         if s >= w0:
             for l, k, cells in ray_dev:
                 probes[s - w0, k] = sim.probe(cells, level=l)
             for l, (a1, a2) in sums.items():
                 sim.accumulate(a1, a2, level=l)
-        if log and s % 1000 == 999:
-            log("cylinder levels %d/%d coarse steps %.1fs" % (s + 1, coarse_steps,
+        if log and (s + 1) * every % 1000 == 0:
+            log("cylinder levels %d/%d coarse steps %.1fs" % ((s + 1) * every, coarse_steps,
                                                               time.time() - t0))
     sim.sync()
     elapsed = time.time() - t0
     fine_dt = 2 ** (levels - 1)             # fine steps per coarse step
+    sdt = every * fine_dt                   # fine steps per sample
     cd, cl = A.force_coefficients(forces.cpu().numpy(), 1.0, U, D)
     cd_w, cl_w = cd[w0:], cl[w0:]
-    # times in fine-level steps: one sample per coarse step
-    st = A.strouhal(cl_w, D, U, dt=fine_dt)
-    f_shed = (st if st else A.peak_frequency(cl_w, fine_dt) * D / U) * U / D
+    st = A.strouhal(cl_w, D, U, dt=sdt)
+    f_shed = (st if st else A.peak_frequency(cl_w, sdt) * D / U) * U / D
     rms_ring = np.zeros(len(ring_angles))
     for l, (a1, a2) in sums.items():
         k = ring_lev == l
-        r = A.rms_from_sums(a1.cpu().numpy(), a2.cpu().numpy(), window) * CS * CS
+        r = A.rms_from_sums(a1.cpu().numpy(), a2.cpu().numpy(), wsamp) * CS * CS
         rms_ring[k] = r[ring_cell[k]]
     p = probes.cpu().numpy() * CS * CS
-    # level-0 samples are one coarse step apart; the tone's frequency there
-    # is f_shed per fine step times fine_dt
-    amp = np.array([A.tone_amplitude(p[:, j], f_shed * fine_dt, 1.0) for j in range(p.shape[1])])
+    # level-0 samples are `every` coarse steps apart: the tone's frequency
+    # per sample is f_shed (per fine step) times sdt
+    amp = np.array([A.tone_amplitude(p[:, j], f_shed * sdt, 1.0) for j in range(p.shape[1])])
     lam0 = CS / (f_shed * fine_dt)          # acoustic wavelength in level-0 cells
     far = ray_r >= lam0
     # overall level at one wavelength, extrapolated to the farthest ray
@@ -178,8 +182,8 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
     L2x = float(A.extrapolate_level(L1, ray_r[i1], ray_r[i2], spreading="cylindrical"))
     # one-third-octave levels at the farthest point (frequencies per level-0
     # step); the band holding the shedding tone should dominate
-    fc, flo, fhi = A.third_octave_bands(0.1 * f_shed * fine_dt, 8.0 * f_shed * fine_dt,
-                                        f_ref=f_shed * fine_dt)
+    fc, flo, fhi = A.third_octave_bands(0.1 * f_shed * sdt, 4.0 * f_shed * sdt,
+                                        f_ref=f_shed * sdt)
     bands = A.band_levels(p[:, i2], 1.0, fc, flo, fhi, p_ref)
     k = int(np.argmax(bands))
     ups = sim.updates_per_step
@@ -190,7 +194,7 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
         storage=storage, layer_D=list(layer_D), chi_max=chi_max, coarse_steps=coarse_steps,
         window_coarse_steps=window,
         st=None if st is None else round(st, 4),
-        st_spectrum=round(A.peak_frequency(cl_w, fine_dt) * D / U, 4),
+        st_spectrum=round(A.peak_frequency(cl_w, sdt) * D / U, 4),
         cl_amplitude=round(A.amplitude(cl_w), 4),
         cl_rms_sqrt2=round(float(cl_w.std() * math.sqrt(2)), 4),
         cd_mean=round(float(cd_w.mean()), 4),
@@ -203,7 +207,7 @@ def run(levels=4, D=32, extent=160.0, halfwidths=(24.0, 10.0, 4.0), downstream=1
         oaspl_db=dict(r1_D=round(float(ray_r[i1]) / D0, 2), at_r1=round(L1, 2),
                       r2_D=round(float(ray_r[i2]) / D0, 2), at_r2=round(L2, 2),
                       r2_from_r1_cylindrical=round(L2x, 2), p_ref=p_ref),
-        third_octave_peak=dict(band_centre_over_f_shed=round(float(fc[k] / (f_shed * fine_dt)), 4),
+        third_octave_peak=dict(band_centre_over_f_shed=round(float(fc[k] / (f_shed * sdt)), 4),
                                level_db=round(float(bands[k]), 2),
                                next_highest_db=round(float(np.sort(bands)[-2]), 2)),
         wave_decay_exponent=round(A.decay_exponent(ray_r, amp), 3),

@@ -99,7 +99,7 @@ enum {
   LBM_EDEVICE = -3,     /* HIP runtime error */
   LBM_EUNSTABLE = -4,   /* a non-finite or non-positive density was seen */
   LBM_ESTATE = -5,      /* call out of order (e.g. step before init) */
-  LBM_EUNSUPPORTED = -6 /* valid request this build does not implement */
+  LBM_EUNSUPPORTED = -6 /* valid request the library does not implement */
 };
 
 /* levels of a refined context: level 0 plus up to four nested 2:1 boxes

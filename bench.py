@@ -193,6 +193,78 @@ def time_steps(sim, torch, steps):
     return a.elapsed_time(b)
 
 
+def slab_rehearsal(lbm, torch, n, fields, steps, headline_mlups, k=8):
+    """The headline grid spread over k GPUs in z-slabs, on this one GPU.
+
+    share: one GPU's n x n x (n/k) slab with both z faces cut (LBM_HALO),
+    its sweep timed alone (halo pack fused into it) and then with its halos
+    moved each step (here to itself: two device copies of the crossing
+    populations, the stand-in for grouped send/recv over xGMI);
+    all_slabs: the k slabs stepped in lockstep on this GPU with the exchange
+    between steps, against the undivided grid's throughput."""
+    from paper_1710_02065_amd.slabs import Slabs
+    rho, u = fields
+    nz = n // k
+    cells = n * n * nz
+    sim = lbm.Simulation(lattice=19, shape=(n, n, nz), tau=0.52, storage="f32",
+                         face_bc=(0, 0, 0, 0, lbm.LBM_HALO, lbm.LBM_HALO))
+    sim.init(rho[:cells].contiguous(), u[:, :cells].contiguous())
+    ring = [sim.ctx]
+    for _ in range(20):
+        sim.step(1)
+        lbm.lbm_halo_exchange(ring, True)
+    sim.sync()
+    sim.block = lbm.lbm_autotune(sim.ctx, 2)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def sweep_only():
+        sim.step(1)
+
+    def sweep_and_exchange():
+        sim.step(1)
+        lbm.lbm_halo_exchange(ring, True)
+
+    ms_sweep = timed(sweep_only, steps)
+    ms_both = timed(sweep_and_exchange, steps)
+    sim.sync()
+    _, _, hb = lbm.lbm_halo_buffers(sim.ctx, 0)
+    share = dict(shape=[n, n, nz], mlups=round(cells / (ms_sweep * 1e3), 1),
+                 hbm_gbs=round(152 * cells / (ms_sweep / 1e3) / 1e9, 1),
+                 sweep_us=round(ms_sweep * 1e3, 2),
+                 exchange_us=round((ms_both - ms_sweep) * 1e3, 2),
+                 halo_bytes_per_cut_and_direction=hb, workgroup=sim.block)
+    del sim
+    torch.cuda.empty_cache()
+    sl = Slabs(k, (n, n, n), lattice=19, tau=0.52, storage="f32")
+    sl.init(rho, u)
+    sl.step(10)
+    sl.sync()
+    ms_all = timed(lambda: sl.step(1), max(steps // k, 20))
+    sl.sync()
+    sl.close()
+    del sl
+    torch.cuda.empty_cache()
+    mlups_all = n ** 3 / (ms_all * 1e3)
+    return {"workload": "D3Q19 %d^3 FP32 (the headline grid) in %d z-slabs of %d planes"
+                        % (n, k, nz),
+            "share": share,
+            "all_slabs_on_one_gpu": dict(mlups=round(mlups_all, 1),
+                                         vs_undivided=round(mlups_all / headline_mlups, 3)),
+            "note": "one GPU's share timed alone; a k-GPU run would step the k shares "
+                    "concurrently with the exchange on the links (not measured here)"}
+
+
 def other_configs(lbm, torch, steps, shedding_steps,
                   which=("c1", "c2", "cylinder_levels", "stability", "c4")):
     """Full-size runs of the other single-GPU configurations (not the
@@ -385,6 +457,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-sharding", action="store_true")
     ap.add_argument("--config-steps", type=int, default=500)
     ap.add_argument("--configs", default="c1,c2,cylinder_levels,stability,c4",
                     help="comma-separated subset of the other configurations to run")
@@ -404,7 +477,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the library runs on one GPU only; --gpus %d is not supported "
-              "(the multi-GPU z-slab decomposition is a design note, not a measured path)"
+              "(the z-slab decomposition is timed on one GPU under \"sharding\")"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -515,6 +588,9 @@ def main():
     if precision:
         out["precision_vs_f64_build"] = precision
     out["config"]["workgroup"] = wg32
+    if not args.no_sharding and n % 8 == 0:
+        log("slab decomposition rehearsal (8 z-slabs)")
+        out["sharding"] = slab_rehearsal(lbm, torch, n, fields, min(args.steps, 500), mlups32)
     if not args.no_configs:
         log("other configurations")
         out["configs"] = other_configs(lbm, torch, args.config_steps, args.shedding_steps,

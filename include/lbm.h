@@ -76,8 +76,22 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_M64 = 4, LBM_M3
  *   PERIODIC: wrap-around.
  *   FREESLIP: specular reflection, wall half a cell outside the face row.
  *   OUTFLOW:  zero gradient, a population entering through the face is
- *             copied from the face row. */
-enum { LBM_PERIODIC = 0, LBM_FREESLIP = 1, LBM_OUTFLOW = 2 };
+ *             copied from the face row.
+ *   HALO:     a cut of a domain split into slabs along its last axis (z in
+ *             3D, y on D2Q9; the other faces of that axis only): each
+ *             population entering through the face is the post-collision
+ *             value of the neighbouring subdomain's face-plane cell it
+ *             streams from (that cell found by the rules of the other
+ *             axes), read from this context's receive buffer; each step
+ *             writes the populations leaving through the face into the send
+ *             buffer (lbm_halo_buffers, lbm_halo_exchange).  The stepping
+ *             equals that of the undivided grid: same operations, same
+ *             values.  Conditions: no refinement, no absorbing-layer width
+ *             on the face, no SOLID cell in the face plane (both subdomains'
+ *             face planes, each checked by its own lbm_init), one step per
+ *             lbm_step call.  Inlet noise is drawn from the subdomain's own
+ *             cell numbering. */
+enum { LBM_PERIODIC = 0, LBM_FREESLIP = 1, LBM_OUTFLOW = 2, LBM_HALO = 3 };
 
 /* cell kinds in the mask.
  *   FLUID: streamed and collided.
@@ -140,7 +154,8 @@ typedef struct lbm_config {
   double rho0;           /* rest density (also the storage shift) */
   double ma;             /* inlet Mach number: U = ma * cs along u_dir */
   double u_dir[3];       /* inlet direction (need not be normalised) */
-  int32_t face_bc[6];    /* LBM_PERIODIC / LBM_FREESLIP / LBM_OUTFLOW */
+  int32_t face_bc[6];    /* LBM_PERIODIC / LBM_FREESLIP / LBM_OUTFLOW /
+                            LBM_HALO */
   int32_t sponge_width[6]; /* absorbing-layer width in coarse cells, per face */
   double chi_max;        /* sponge strength maximum, 0 <= chi_max < 4 tau */
   double rho_ref;        /* sponge reference density */
@@ -207,7 +222,7 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
              const double* pi_neq, const uint8_t* mask);
 
 /* Enqueue n coarse steps (level l + 1 takes two steps per step of level l
- * on a refined context).
+ * on a refined context; n <= 1 with LBM_HALO faces, else LBM_EINVAL).
  * Returns after enqueueing.  Kernel-side instability is recorded in a sticky
  * flag reported by lbm_sync / lbm_moments. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
@@ -302,7 +317,8 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
  * launches between contexts: the contexts are grouped by lattice, storage,
  * sweep path (fully periodic or not) and workgroup size, and each group
  * advances through one persistent launch per step.  All contexts must be
- * unrefined, on one device and one stream, and initialised.  Each context's
+ * unrefined, without halo faces, on one device and one stream, and
+ * initialised.  Each context's
  * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */
 int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
 
@@ -312,6 +328,36 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
  * afterwards), keep the fastest, and return it (> 0) or a negative
  * status. */
 int lbm_autotune(lbm_ctx* ctx, int trials);
+
+/* Slab decomposition (face rule LBM_HALO; the streaming step of eq.
+ * optimizedLB across a cut).  Library-owned device buffers of the halo face
+ * on side 0 (low) or 1 (high) of the last axis, valid until lbm_destroy:
+ *   send: the post-collision populations of this context's face-plane cells
+ *         that leave through the face, written by every lbm_step and by
+ *         lbm_init / lbm_set_populations;
+ *   recv: what lbm_step reads for the populations entering through the
+ *         face; before each lbm_step it must hold the neighbour's send
+ *         buffer of the opposite side.  lbm_init fills it from this
+ *         context's own face plane (a zero-gradient face until the first
+ *         exchange).
+ * Both hold *bytes bytes: [k][cell of the face plane] in the storage format
+ * (stored values, shifted for F32S/F16S), k = rank, in the documented
+ * direction order, among the directions with xi_last = -1 (send low, recv
+ * high) or +1 (send high, recv low): 3 on D2Q9, 5 on D3Q19, 9 on D3Q27;
+ * plane cells x + nx*y (3D) or x (D2Q9).  A caller on several GPUs moves
+ * send to the neighbour's recv itself (e.g. grouped RCCL send/recv) after
+ * lbm_init, lbm_set_populations and every lbm_step.  LBM_EINVAL if the face
+ * is not LBM_HALO, LBM_ESTATE before lbm_init. */
+int lbm_halo_buffers(lbm_ctx* ctx, int side, void** send, void** recv, size_t* bytes);
+
+/* The same exchange between n initialised contexts on one device and one
+ * stream, subdomain k + 1 above subdomain k along the last axis (and, with
+ * periodic != 0, subdomain 0 above subdomain n - 1): asynchronous device
+ * copies of each send buffer into the neighbour's receive buffer, on the
+ * shared stream.  The contexts must agree on lattice, storage, rho0 and the
+ * face plane, and carry every halo face the chain needs (LBM_EINVAL
+ * otherwise).  With n = 1 and periodic, the context is its own neighbour. */
+int lbm_halo_exchange(lbm_ctx* const* ctxs, int n, int periodic);
 
 /* Release the context and the memory it allocated.  NULL-safe. */
 void lbm_destroy(lbm_ctx* ctx);

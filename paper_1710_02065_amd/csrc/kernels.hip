@@ -36,10 +36,11 @@ __device__ __forceinline__ int dir_rt(int x, int y, int z) {
 // Pull under the face rules and the mask (left side of eq. optimizedLB read
 // backwards): the source of population i is x - xi_i, mapped axis by axis
 // (periodic wrap, free-slip reflection with the population mirrored,
-// zero-gradient clamp); a link whose source is SOLID is bounced back
-// halfway from this cell.  Applied as corrections to the periodic pull
-// already in raw[]: only the directions whose source crosses a non-periodic
-// face, or (for cells flagged kNearSolid) is SOLID, are loaded again.
+// zero-gradient clamp, or the neighbour subdomain's values through a halo
+// face); a link whose source is SOLID is bounced back halfway from this
+// cell.  Applied as corrections to the periodic pull already in raw[]: only
+// the directions whose source crosses a non-periodic face, or (for cells
+// flagged kNearSolid) is SOLID, are loaded again.
 // ------------------------------------------------------------------------
 template <class L, class S>
 __device__ __forceinline__ void pull_fixup(const SweepArgs<S>& a, uint32_t x, uint32_t y,
@@ -54,6 +55,7 @@ __device__ __forceinline__ void pull_fixup(const SweepArgs<S>& a, uint32_t x, ui
     int32_t s[3] = {(int32_t)x - v.x, (int32_t)y - v.y, (int32_t)z - v.z};
     bool flip[3] = {false, false, false};
     bool cross = false;
+    int hs = -1;  // halo side crossed (only the last axis has halo faces)
 #pragma unroll
     for (int ax = 0; ax < L::D; ++ax) {
       if (vv[ax] == 0) continue;
@@ -66,12 +68,13 @@ __device__ __forceinline__ void pull_fixup(const SweepArgs<S>& a, uint32_t x, ui
         } else {
           s[ax] = lo ? 0 : n - 1;
           flip[ax] = (bc == kFreeSlip);
+          if (bc == kHalo) hs = hi ? 1 : 0;
           cross = true;
         }
       }
     }
     const uint32_t src = ((uint32_t)s[2] * a.ny + (uint32_t)s[1]) * a.nx + (uint32_t)s[0];
-    if (near_solid && (a.mask[src] & kKindBits) == kSolid) {
+    if (near_solid && hs < 0 && (a.mask[src] & kKindBits) == kSolid) {
       // halfway bounce-back: the population that left this cell towards
       // the wall comes back reversed (same weight, so the same shift)
       constexpr int o = opposite<L>(i);
@@ -81,7 +84,75 @@ __device__ __forceinline__ void pull_fixup(const SweepArgs<S>& a, uint32_t x, ui
       if (flip[0] || flip[1] || flip[2])
         pop = dir_rt<L>(flip[0] ? -v.x : v.x, flip[1] ? -v.y : v.y,
                         flip[2] ? -v.z : v.z);
-      raw[i] = load_pop(a.src + (uint64_t)pop * P, src);
+      if (hs >= 0) {
+        // the source lies in the neighbour's face plane (mapped on the
+        // other axes as above); a free-slip flip acts on the other axes
+        // only, so the row is one of four known at compile time
+        constexpr int r00 = halo_rank<L>(i);
+        constexpr int r10 = halo_rank<L>(find_dir<L>(-v.x, v.y, v.z));
+        constexpr int r01 = halo_rank<L>(find_dir<L>(v.x, -v.y, v.z));
+        constexpr int r11 = halo_rank<L>(find_dir<L>(-v.x, -v.y, v.z));
+        const int r = flip[0] ? (flip[1] ? r11 : r10) : (flip[1] ? r01 : r00);
+        const uint32_t pc = L::D == 3 ? (uint32_t)s[1] * a.nx + (uint32_t)s[0] : (uint32_t)s[0];
+        const typename S::T* rb = hs ? a.hrecv[1] : a.hrecv[0];
+        raw[i] = load_pop(rb + (uint64_t)r * a.hplane, pc);
+      } else {
+        raw[i] = load_pop(a.src + (uint64_t)pop * P, src);
+      }
+    }
+  });
+}
+
+// Halo faces on the periodic path (every other face periodic, no mask): a
+// face-plane cell replaces the populations the periodic pull wrapped across
+// a halo face by the neighbour's values, from the receive buffer at the
+// source wrapped on the other axes.
+template <class L, class S>
+__device__ __forceinline__ void halo_pull_periodic(const SweepArgs<S>& a, uint32_t x,
+                                                   uint32_t y, uint32_t z,
+                                                   typename S::T raw[L::Q]) {
+  const uint32_t zl = L::D == 3 ? z : y, nl = L::D == 3 ? a.nz : a.ny;
+  const bool lo = zl == 0 && a.hrecv[0], hi = zl + 1 == nl && a.hrecv[1];
+  if (!lo && !hi) return;
+  static_for<1, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr Dir v = L::dir(i);
+    constexpr int vl = last_component<L>(v);
+    if constexpr (vl != 0) {
+      if ((vl > 0 && lo) || (vl < 0 && hi)) {
+        int32_t sx = (int32_t)x - v.x;
+        if (sx < 0) sx += (int32_t)a.nx;
+        if (sx >= (int32_t)a.nx) sx -= (int32_t)a.nx;
+        uint32_t pc = (uint32_t)sx;
+        if constexpr (L::D == 3) {
+          int32_t sy = (int32_t)y - v.y;
+          if (sy < 0) sy += (int32_t)a.ny;
+          if (sy >= (int32_t)a.ny) sy -= (int32_t)a.ny;
+          pc += (uint32_t)sy * a.nx;
+        }
+        const typename S::T* rb = vl > 0 ? a.hrecv[0] : a.hrecv[1];
+        raw[i] = load_pop(rb + (uint64_t)halo_rank<L>(i) * a.hplane, pc);
+      }
+    }
+  });
+}
+
+// Pack of a face-plane cell's post-collision populations that leave
+// through a halo face into that face's send buffer.
+template <class L, class S>
+__device__ __forceinline__ void halo_pack(const SweepArgs<S>& a, uint32_t c, uint32_t zl,
+                                          uint32_t nl, const typename S::R post[L::Q]) {
+  using T = typename S::T;
+  const uint32_t pc = c - zl * a.hplane;
+  const bool lo = zl == 0 && a.hsend[0], hi = zl + 1 == nl && a.hsend[1];
+  static_for<1, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int vl = last_component<L>(L::dir(i));
+    constexpr int r = halo_rank<L>(i);
+    if constexpr (vl < 0) {
+      if (lo) a.hsend[0][(uint64_t)r * a.hplane + pc] = (T)post[i];
+    } else if constexpr (vl > 0) {
+      if (hi) a.hsend[1][(uint64_t)r * a.hplane + pc] = (T)post[i];
     }
   });
 }
@@ -145,7 +216,10 @@ __device__ __forceinline__ void record_moments(const SweepArgs<S>& a,
 
 // ------------------------------------------------------------------------
 // The sweep: pull-stream + (sponge) + regularized collision + store.
-// kGeneral = false: every face periodic, no mask, no sponge.
+// kGeneral = false: every face periodic (or a halo face of the last axis),
+// no mask, no sponge.  The solo and
+// the batched sweeps share this code, halo faces included (the batch never
+// has any): one instantiation keeps their results bitwise equal.
 // ------------------------------------------------------------------------
 template <class L, class S, bool kGeneral>
 __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
@@ -165,6 +239,7 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   R rho, drho, j[3], Pm[6];
   if constexpr (!kGeneral) {
     pull_periodic<L, S>(a, c, x, y, z, raw);
+    if (a.hrecv[0] || a.hrecv[1]) halo_pull_periodic<L, S>(a, x, y, z, raw);
     stored_moments<L, S>(raw, a.rho0, drho, j, Pm);
     if constexpr (L::kColl == kCollBGK)
       rho = collide_bgk<L, S>(raw, drho, j, a.omega1, a.rho0, (R)0, a.rho_ref, a.uref, post);
@@ -235,6 +310,11 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
   }
   // stability watchdog: a rare, benign racy store of 1
   if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
+  {
+    const uint32_t zl = L::D == 3 ? z : y, nl = L::D == 3 ? a.nz : a.ny;
+    if ((zl == 0 && a.hsend[0]) || (zl + 1 == nl && a.hsend[1]))
+      halo_pack<L, S>(a, c, zl, nl, post);
+  }
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     store_pop_nt(a.dst + (uint64_t)i * P, (uint32_t)(P * sizeof(T)), c, (T)post[i]);
@@ -610,6 +690,65 @@ __global__ void k_tiles(FlagsArgs a) {
   a.tiles[t] = plain;
 }
 
+// Halo faces outside the sweep (after initialisation or an import of
+// populations): the face planes' leaving populations into the send
+// buffers, as the sweep packs them, and, with `entering`, the same planes'
+// entering populations into the receive buffers (the face behaves as a
+// zero-gradient face until the first exchange).
+template <class L, class S>
+__global__ void k_halo_pack(HaloArgs h) {
+  using T = typename S::T;
+  const uint32_t pc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pc >= h.hplane) return;
+  const T* src = (const T*)h.src;
+  const uint32_t nl = L::D == 3 ? h.nz : h.ny;
+  for (int side = 0; side < 2; ++side) {
+    if (!h.hsend[side]) continue;
+    const uint32_t zl = side ? nl - 1 : 0;
+    const uint64_t c = (uint64_t)zl * h.hplane + pc;
+    T* send = (T*)h.hsend[side];
+    T* recv = (T*)h.hrecv[side];
+    static_for<1, L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int vl = last_component<L>(L::dir(i));
+      const T v = src[(uint64_t)i * h.pstride + c];
+      const uint64_t o = (uint64_t)halo_rank<L>(i) * h.hplane + pc;
+      if (vl == (side ? 1 : -1)) send[o] = v;
+      if (h.entering && vl == (side ? -1 : 1)) recv[o] = v;
+    });
+  }
+}
+
+template <class L>
+static void halo_pack_l(int storage, const HaloArgs& a, hipStream_t st) {
+  const uint32_t blocks = (a.hplane + 255) / 256;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL((k_halo_pack<L, StoreF64>), dim3(blocks), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_halo_pack<L, StoreF32>), dim3(blocks), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_halo_pack<L, StoreF32S>), dim3(blocks), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_halo_pack<L, StoreF16S>), dim3(blocks), dim3(256), 0, st, a); break;
+  }
+}
+
+hipError_t launch_halo_pack(int lattice, int storage, const HaloArgs& a, hipStream_t st) {
+  switch (lattice) {
+    case 9: halo_pack_l<Lattice<9>>(storage, a, st); break;
+    case 19: halo_pack_l<Lattice<19>>(storage, a, st); break;
+    case 27: halo_pack_l<Lattice<27>>(storage, a, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int halo_count_of(int lattice) {
+  switch (lattice) {
+    case 9: return halo_count<Lattice<9>>();
+    case 19: return halo_count<Lattice<19>>();
+    case 27: return halo_count<Lattice<27>>();
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------------
 // Two-level refinement kernels (Sec. II.B)
 // ------------------------------------------------------------------------
@@ -831,6 +970,11 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
     a.box_hi[k] = h.box_hi[k];
   }
   a.rec_n = h.rec_n;
+  for (int k = 0; k < 2; ++k) {
+    a.hrecv[k] = (const T*)h.hrecv[k];
+    a.hsend[k] = (T*)h.hsend[k];
+  }
+  a.hplane = h.hplane;
   return a;
 }
 

@@ -23,7 +23,7 @@
 
 namespace hrlbm {
 
-enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2 };
+enum : int { kPeriodic = 0, kFreeSlip = 1, kOutflow = 2, kHalo = 3 };
 // cell kinds: the public FLUID/SOLID/INLET, and the refinement roles
 // COVERED (coarse node under the fine patch), IMPORT (coarse node rebuilt
 // from fine data), RING (fine node rebuilt from coarse data); cells of the
@@ -180,7 +180,48 @@ struct SweepArgs {
   // absorbing layer given per cell: chi, rho_ref, u_ref (5 x ncell), read
   // for cells flagged kFieldSponge; nullptr: none
   const R* sp;
+  // halo faces of the last axis (slab decomposition), side 0 = low, 1 =
+  // high: populations entering through the face are read from hrecv[side],
+  // those leaving are written to hsend[side] (nullptr: no pack), each
+  // [rank][cell of the face plane] with hplane cells per plane; rank as in
+  // halo_rank()
+  const T* hrecv[2];
+  T* hsend[2];
+  uint32_t hplane;
 };
+
+// Component of a direction along the last axis (the slab-cut axis: z in
+// 3D, y on D2Q9).
+template <class L>
+__host__ __device__ constexpr int last_component(const Dir& v) {
+  return L::D == 3 ? v.z : v.y;
+}
+// Rank of direction i among the directions with the same last-axis
+// component, in direction order: the row of the halo buffers holding it.
+template <class L>
+struct HaloRankTable {
+  int v[27];
+  constexpr HaloRankTable() : v() {
+    for (int i = 0; i < L::Q; ++i) {
+      int r = 0;
+      for (int j = 0; j < i; ++j)
+        if (last_component<L>(L::dir(j)) == last_component<L>(L::dir(i))) ++r;
+      v[i] = r;
+    }
+  }
+};
+template <class L>
+__host__ __device__ constexpr int halo_rank(int i) {
+  return HaloRankTable<L>{}.v[i];
+}
+// directions crossing one halo face: 3 (D2Q9), 5 (D3Q19), 9 (D3Q27)
+template <class L>
+__host__ __device__ constexpr int halo_count() {
+  int n = 0;
+  for (int i = 0; i < L::Q; ++i)
+    if (last_component<L>(L::dir(i)) == 1) ++n;
+  return n;
+}
 
 // Band of a child level whose pre-collision moments its parent's IMPORT
 // nodes filter: the parent's IMPORT shell [lo+1, hi-1] lies on child index 2

@@ -44,6 +44,21 @@ struct SweepHost {
   void* recf;
   // absorbing layer given per cell (5 x N values of the compute type)
   const void* sp;
+  // halo faces of the last axis, side 0 = low, 1 = high (nullptr: none;
+  // hsend nullptr: the sweep does not pack); hplane cells per face plane
+  const void* hrecv[2];
+  void* hsend[2];
+  uint32_t hplane;
+};
+
+// Halo faces packed outside the sweep (k_halo_pack).
+struct HaloArgs {
+  const void* src;
+  void* hsend[2];  // nullptr: side has no halo face
+  void* hrecv[2];
+  uint32_t nx, ny, nz, hplane;
+  uint64_t pstride;
+  int entering;    // also fill the receive buffers from the own face plane
 };
 
 // Absorbing layer given per cell: FP64 inputs converted into `sp`
@@ -240,6 +255,9 @@ hipError_t launch_get_pop(int lattice, int storage, const PopArgs& a,
 hipError_t launch_set_pop(int lattice, int storage, const PopArgs& a,
                           uint32_t n, hipStream_t st);
 hipError_t launch_roles(const RolesArgs& a, uint32_t n, hipStream_t st);
+hipError_t launch_halo_pack(int lattice, int storage, const HaloArgs& a, hipStream_t st);
+// directions crossing one halo face (3, 5 or 9 for lattice 9, 19, 27)
+int halo_count_of(int lattice);
 hipError_t launch_flags(int lattice, const FlagsArgs& a, hipStream_t st);
 hipError_t launch_record_fields(int lattice, int storage, const RecordFieldsArgs& a,
                                 uint32_t n, hipStream_t st);

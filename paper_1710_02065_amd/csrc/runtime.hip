@@ -78,6 +78,13 @@ static bool refined(const lbm_config& c) {
   return false;
 }
 
+int halo_face(int lattice, int side) { return (lattice == LBM_D2Q9 ? 2 : 4) + side; }
+
+bool has_halo(const lbm_config& c) {
+  return c.face_bc[halo_face(c.lattice, 0)] == LBM_HALO ||
+         c.face_bc[halo_face(c.lattice, 1)] == LBM_HALO;
+}
+
 static double inlet_speed(const lbm_config& c) {
   return c.ma * std::sqrt(1.0 / 3.0);
 }
@@ -138,8 +145,16 @@ int validate(const lbm_config* cfg) {
       return set_error(LBM_EINVAL, "axis %d: both faces periodic or neither", a);
   }
   for (int f = 0; f < 6; ++f) {
-    if (c.face_bc[f] < LBM_PERIODIC || c.face_bc[f] > LBM_OUTFLOW)
+    if (c.face_bc[f] < LBM_PERIODIC || c.face_bc[f] > LBM_HALO)
       return set_error(LBM_EINVAL, "face %d: unknown rule %d", f, c.face_bc[f]);
+    if (c.face_bc[f] == LBM_HALO) {
+      if (f / 2 != halo_face(c.lattice, 0) / 2)
+        return set_error(LBM_EINVAL, "face %d: LBM_HALO only on the faces of the last axis "
+                         "(z in 3D, y on D2Q9)", f);
+      // the analytic layer profile would use this subdomain's own extent
+      if (c.sponge_width[f] != 0)
+        return set_error(LBM_EINVAL, "face %d: no absorbing layer on a halo face", f);
+    }
     const int64_t n = f < 2 ? c.nx : (f < 4 ? c.ny : c.nz);
     if (c.sponge_width[f] < 0 || c.sponge_width[f] > n)
       return set_error(LBM_EINVAL, "face %d: sponge width %d", f, c.sponge_width[f]);
@@ -171,6 +186,8 @@ int validate(const lbm_config* cfg) {
     if (c.flags & (LBM_BGK | LBM_MRT))
       return set_error(LBM_EINVAL, "moment storage needs the regularized collision");
   }
+  if (has_halo(c) && (refined(c) || c.nest_count > 0))
+    return set_error(LBM_EINVAL, "halo faces need an unrefined context");
   if (refined(c)) return validate_refinement(c);
   return LBM_OK;
 }
@@ -198,6 +215,14 @@ void plan_layout(lbm_ctx* ctx) {
   for (int l = 0; l < ctx->nlevels; ++l) {
     Level& L = ctx->lv[l];
     level_layout(L, c.lattice, c.storage, (c.flags & LBM_SPONGE_FIELD) != 0);
+    if (l == 0 && has_halo(c)) {
+      // send low, send high, receive low, receive high
+      L.hplane = (uint32_t)(c.lattice == LBM_D2Q9 ? L.nx : L.nx * L.ny);
+      L.halo_bytes = align_up((size_t)halo_count_of(c.lattice) * L.hplane *
+                                  storage_bytes(c.storage), 256);
+      L.off_halo = L.bytes;
+      L.bytes += 4 * L.halo_bytes;
+    }
     L.base_off = off;
     off += L.bytes;
   }
@@ -311,6 +336,11 @@ void assign_pointers(lbm_ctx* ctx) {
     L.mask = (uint8_t*)(b + L.off_mask);
     L.tiles = (uint8_t*)(b + L.off_tiles);
     L.sp = (ctx->cfg.flags & LBM_SPONGE_FIELD) ? (void*)(b + L.off_sponge) : nullptr;
+    for (int side = 0; side < 2; ++side) {
+      const bool on = L.halo_bytes && L.face[halo_face(ctx->cfg.lattice, side)] == LBM_HALO;
+      L.hsend[side] = on ? b + L.off_halo + side * L.halo_bytes : nullptr;
+      L.hrecv[side] = on ? b + L.off_halo + (2 + side) * L.halo_bytes : nullptr;
+    }
   }
   assign_interface_pointers(ctx);
 }
@@ -368,17 +398,24 @@ SweepHost sweep_args(const lbm_ctx* ctx, int l, int src_buf, uint64_t t_new) {
     h.sp = L.sp;
     h.chi_max = 0.0;
   }
+  // halo faces also run on the periodic path (which reads them itself)
+  // when every other face is periodic
   bool general = L.has_mask || L.chi_max > 0;
   for (int f = 0; f < 6; ++f) {
     h.face[f] = L.face[f];
     h.sponge[f] = L.sponge[f];
-    if (L.face[f] != LBM_PERIODIC) general = true;
+    if (L.face[f] != LBM_PERIODIC && L.face[f] != LBM_HALO) general = true;
   }
   h.seed = c.seed;
   h.t_new = t_new;
   h.level = L.level;
   h.lstride = ctx->nlevels > 2 ? (uint32_t)ctx->nlevels : 2u;
   h.general = general;
+  for (int side = 0; side < 2; ++side) {
+    h.hrecv[side] = L.hrecv[side];
+    h.hsend[side] = L.hsend[side];
+  }
+  h.hplane = L.hplane;
   return h;
 }
 
@@ -541,6 +578,10 @@ static int step_graph(lbm_ctx* ctx, int64_t chunks, hipStream_t st) {
 
 int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st) {
   if (n < 0) return set_error(LBM_EINVAL, "negative step count");
+  if (n > 1 && has_halo(ctx->cfg))
+    return set_error(LBM_EINVAL,
+                     "a context with halo faces advances one step per call (the halos are "
+                     "exchanged between steps)");
   if (graphs_allowed(ctx) && ctx->nlevels > 1 && n >= kRefinedGraphSteps) {
     const int64_t chunks = n / kRefinedGraphSteps;
     int rc = step_graph_refined(ctx, chunks, st);
@@ -553,6 +594,28 @@ int step_ctx(lbm_ctx* ctx, int64_t n, hipStream_t st) {
     n -= chunks * kGraphSteps;
   }
   return step_eager(ctx, n, st);
+}
+
+// Halo faces from the current state of level 0 outside the sweep: send
+// buffers always, receive buffers with `entering` (see k_halo_pack).
+static int pack_halos(lbm_ctx* ctx, bool entering) {
+  const Level& L = ctx->lv[0];
+  if (!L.hplane) return LBM_OK;
+  HaloArgs a{};
+  a.src = L.buf[L.cur];
+  for (int side = 0; side < 2; ++side) {
+    a.hsend[side] = L.hsend[side];
+    a.hrecv[side] = L.hrecv[side];
+  }
+  a.nx = (uint32_t)L.nx;
+  a.ny = (uint32_t)L.ny;
+  a.nz = (uint32_t)L.nz;
+  a.hplane = L.hplane;
+  a.pstride = L.pstride;
+  a.entering = entering ? 1 : 0;
+  hipError_t e = launch_halo_pack(ctx->cfg.lattice, ctx->cfg.storage, a, ctx->stream);
+  if (e != hipSuccess) return hip_error(e, "halo pack launch");
+  return LBM_OK;
 }
 
 }  // namespace hrlbm
@@ -599,7 +662,7 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
   bool general = mask != nullptr || ctx->nlevels > 1 || L.chi_max > 0 ||
                  (ctx->cfg.flags & LBM_SPONGE_FIELD);
   for (int f = 0; f < 6; ++f)
-    if (L.face[f] != LBM_PERIODIC) general = true;
+    if (L.face[f] != LBM_PERIODIC && L.face[f] != LBM_HALO) general = true;
   L.has_mask = general;
   if (ctx->nlevels > 1) {
     rc = refined_init_level(ctx, level, rho, u, pi_neq);
@@ -629,11 +692,24 @@ int lbm_init(lbm_ctx* ctx, int level, const double* rho, const double* u,
       }
     for (uint8_t m : hm)
       if (m > LBM_INLET) return set_error(LBM_EINVAL, "mask value %u", (unsigned)m);
+    // a link across a halo face never meets a wall: the face planes of both
+    // subdomains hold no SOLID cell (each side checks its own)
+    for (int side = 0; side < 2; ++side) {
+      if (!L.hsend[side]) continue;
+      const int64_t nl = ctx->cfg.lattice == LBM_D2Q9 ? L.ny : L.nz;
+      const size_t c0 = (size_t)(side ? nl - 1 : 0) * L.hplane;
+      for (size_t pc = 0; pc < L.hplane; ++pc)
+        if (hm[c0 + pc] == LBM_SOLID)
+          return set_error(LBM_EINVAL, "SOLID cell on the plane of halo face %d",
+                           halo_face(ctx->cfg.lattice, side));
+    }
   }
   L.cur = 0;
   L.t = 0;
   L.field_sponge = false;
   L.initialised = true;
+  rc = pack_halos(ctx, true);
+  if (rc != LBM_OK) return rc;
   if (ctx->cfg.block == 0) {
     const int tb = tuned_block(ctx);
     if (tb > 0) ctx->block = tb;
@@ -901,6 +977,55 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
                                       ctx->stream);
   if (e != hipSuccess) return hip_error(e, "set_populations launch");
   if (ctx->nlevels > 1) return refined_after_set(ctx, level);
+  return pack_halos(ctx, false);
+}
+
+int lbm_halo_buffers(lbm_ctx* ctx, int side, void** send, void** recv, size_t* bytes) {
+  if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
+  if (side != 0 && side != 1) return set_error(LBM_EINVAL, "side %d: 0 (low) or 1 (high)", side);
+  const Level& L = ctx->lv[0];
+  if (ctx->cfg.face_bc[halo_face(ctx->cfg.lattice, side)] != LBM_HALO)
+    return set_error(LBM_EINVAL, "face %d is not LBM_HALO", halo_face(ctx->cfg.lattice, side));
+  if (!ctx->mem) return set_error(LBM_ESTATE, "no device memory yet (call lbm_init)");
+  if (send) *send = L.hsend[side];
+  if (recv) *recv = L.hrecv[side];
+  if (bytes)
+    *bytes = (size_t)halo_count_of(ctx->cfg.lattice) * L.hplane * storage_bytes(ctx->cfg.storage);
+  return LBM_OK;
+}
+
+int lbm_halo_exchange(lbm_ctx* const* ctxs, int n, int periodic) {
+  if (n < 1 || !ctxs) return set_error(LBM_EINVAL, "exchange arguments");
+  for (int k = 0; k < n; ++k) {
+    int rc = check_ready(ctxs[k]);
+    if (rc != LBM_OK) return rc;
+    const lbm_config &c = ctxs[k]->cfg, &c0 = ctxs[0]->cfg;
+    if (ctxs[k]->device != ctxs[0]->device || ctxs[k]->stream != ctxs[0]->stream)
+      return set_error(LBM_EINVAL, "exchanged contexts must share device and stream");
+    if (c.lattice != c0.lattice || c.storage != c0.storage || c.nx != c0.nx ||
+        (c.lattice != LBM_D2Q9 && c.ny != c0.ny) || c.rho0 != c0.rho0)
+      return set_error(LBM_EINVAL, "context %d: lattice, storage, rho0 or face plane differs", k);
+    const bool lo_needed = k > 0 || periodic, hi_needed = k < n - 1 || periodic;
+    if ((lo_needed && !ctxs[k]->lv[0].hrecv[0]) || (hi_needed && !ctxs[k]->lv[0].hrecv[1]))
+      return set_error(LBM_EINVAL, "context %d lacks a halo face the chain needs", k);
+  }
+  int rc = ensure_device(ctxs[0]);
+  if (rc != LBM_OK) return rc;
+  size_t bytes = 0;
+  rc = lbm_halo_buffers(ctxs[0], ctxs[0]->lv[0].hrecv[0] ? 0 : 1, nullptr, nullptr, &bytes);
+  if (rc != LBM_OK) return rc;
+  // subdomain k + 1 lies above k; with `periodic` subdomain 0 lies above n - 1
+  const int pairs = periodic ? n : n - 1;
+  for (int k = 0; k < pairs; ++k) {
+    const Level& below = ctxs[k]->lv[0];
+    const Level& above = ctxs[(k + 1) % n]->lv[0];
+    hipError_t e = hipMemcpyAsync(above.hrecv[0], below.hsend[1], bytes,
+                                  hipMemcpyDeviceToDevice, ctxs[0]->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(below.hrecv[1], above.hsend[0], bytes, hipMemcpyDeviceToDevice,
+                         ctxs[0]->stream);
+    if (e != hipSuccess) return hip_error(e, "halo copy");
+  }
   return LBM_OK;
 }
 

@@ -27,6 +27,13 @@ struct Level {
   uint8_t* mask = nullptr;
   uint8_t* tiles = nullptr;  // per 64-cell tile: 1 = plain fluid (see k_tiles)
   void* sp = nullptr;        // per-cell absorbing layer (LBM_SPONGE_FIELD)
+  // halo faces of the last axis (slab decomposition): send and receive
+  // buffers per side (nullptr where the face is not LBM_HALO), each
+  // halo_bytes, hplane cells per face plane
+  size_t off_halo = 0, halo_bytes = 0;
+  void* hsend[2] = {nullptr, nullptr};
+  void* hrecv[2] = {nullptr, nullptr};
+  uint32_t hplane = 0;
   bool field_sponge = false; // set by lbm_set_sponge since the last init
   bool has_mask = false;
   bool initialised = false;
@@ -92,6 +99,10 @@ int lattice_dim(int lattice);
 size_t storage_bytes(int storage);
 uint64_t pop_stride(uint64_t n);
 int validate(const lbm_config* cfg);
+// face index of side 0 (low) / 1 (high) of the last axis, the only axis
+// that may carry LBM_HALO faces
+int halo_face(int lattice, int side);
+bool has_halo(const lbm_config& c);
 void plan_layout(lbm_ctx* ctx);
 void assign_pointers(lbm_ctx* ctx);
 int ensure_device(const lbm_ctx* ctx);

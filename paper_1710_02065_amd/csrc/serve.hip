@@ -294,6 +294,8 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
       return set_error(LBM_EUNSUPPORTED, "refined contexts cannot be batched");
     if (moment_storage(ctxs[k]->cfg.storage))
       return set_error(LBM_EUNSUPPORTED, "moment-stored contexts cannot be batched");
+    if (has_halo(ctxs[k]->cfg))
+      return set_error(LBM_EUNSUPPORTED, "contexts with halo faces cannot be batched");
     if (ctxs[k]->device != ctxs[0]->device || ctxs[k]->stream != ctxs[0]->stream)
       return set_error(LBM_EINVAL, "batched contexts must share device and stream");
     for (int m = 0; m < k; ++m)
@@ -332,7 +334,9 @@ int lbm_autotune(lbm_ctx* ctx, int trials) {
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e != hipSuccess) return hip_error(e, "autotune events");
-  const SweepHost h = sweep_args(ctx, 0, L.cur, (uint64_t)(L.t + 1));
+  SweepHost h = sweep_args(ctx, 0, L.cur, (uint64_t)(L.t + 1));
+  // the timing sweeps leave the halo send buffers as they are
+  h.hsend[0] = h.hsend[1] = nullptr;
   const int reps = std::max(3, (int)std::min<int64_t>(50, (int64_t)(2e8 / (double)L.N)));
   float best_ms = 1e30f;
   int best = ctx->block;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
 LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 = 9, 19, 27
 LBM_F64, LBM_F32, LBM_F32S, LBM_F16S, LBM_M64, LBM_M32 = 0, 1, 2, 3, 4, 5
-LBM_PERIODIC, LBM_FREESLIP, LBM_OUTFLOW = 0, 1, 2
+LBM_PERIODIC, LBM_FREESLIP, LBM_OUTFLOW, LBM_HALO = 0, 1, 2, 3
 LBM_FLUID, LBM_SOLID, LBM_INLET = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
@@ -34,8 +34,8 @@ EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memo
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
            "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_set_sponge", "lbm_get_populations", "lbm_set_populations",
-           "lbm_step_batch", "lbm_autotune", "lbm_destroy", "lbm_lattice_table",
-           "lbm_last_error"]
+           "lbm_step_batch", "lbm_autotune", "lbm_halo_buffers", "lbm_halo_exchange",
+           "lbm_destroy", "lbm_lattice_table", "lbm_last_error"]
 
 
 class lbm_config(C.Structure):
@@ -98,6 +98,9 @@ def lib():
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_int]
+        L.lbm_halo_buffers.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp),
+                                       C.POINTER(C.c_size_t)]
+        L.lbm_halo_exchange.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_lattice_table.argtypes = [C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
@@ -206,6 +209,20 @@ def lbm_step_batch(ctxs, steps):
 
 def lbm_autotune(ctx, trials=3):
     return _check(lib().lbm_autotune(ctx, trials))
+
+
+def lbm_halo_buffers(ctx, side):
+    """(send, recv, bytes): device addresses of the halo buffers of side 0
+    (low) or 1 (high) of the last axis."""
+    send, recv, nb = C.c_void_p(), C.c_void_p(), C.c_size_t()
+    _check(lib().lbm_halo_buffers(ctx, side, C.byref(send), C.byref(recv), C.byref(nb)))
+    return send.value, recv.value, nb.value
+
+
+def lbm_halo_exchange(ctxs, periodic):
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.value for c in ctxs])
+    return _check(lib().lbm_halo_exchange(arr, n, 1 if periodic else 0))
 
 
 def lbm_destroy(ctx):

@@ -162,3 +162,41 @@ def test_moment_storage_validation_and_size():
     for kw in bad:
         assert required(lattice=19, shape=(16, 16, 16), storage="m32", **kw) == 0, kw
         assert "moment storage" in lbm.lbm_last_error()
+
+
+def test_halo_face_validation_and_size():
+    """LBM_HALO (slab cut): last axis only, no refinement, no face layer on
+    the cut, not with the moment storages; four buffers of the crossing
+    populations of one face plane are added to the context."""
+    base = dict(lattice=19, shape=(16, 12, 10), storage="f32")
+    plain = required(**base)
+    ring = required(face_bc=(0, 0, 0, 0, 3, 3), **base)
+    assert ring - plain >= 4 * 5 * 16 * 12 * 4
+    assert ring - plain < 4 * (5 * 16 * 12 * 4 + 256) + 1024
+    assert required(face_bc=(2, 2, 1, 1, 3, 2), **base) > 0
+    assert required(lattice=9, shape=(30, 20, 1), face_bc=(2, 2, 3, 1, 0, 0)) > 0
+    bad = [(dict(face_bc=(3, 3, 0, 0, 0, 0)), "last axis"),
+           (dict(face_bc=(0, 0, 3, 3, 0, 0)), "last axis"),
+           (dict(lattice=9, shape=(30, 20, 1), face_bc=(3, 3, 0, 0, 0, 0)), "last axis"),
+           (dict(face_bc=(0, 0, 0, 0, 3, 0)), "periodic"),
+           (dict(face_bc=(0, 0, 0, 0, 3, 3), chi_max=0.1, sponge_width=(0, 0, 0, 0, 2, 0)),
+            "absorbing layer"),
+           (dict(face_bc=(2, 2, 2, 2, 3, 3), refine_lo=(4, 4, 4), refine_hi=(10, 8, 6)),
+            "unrefined"),
+           (dict(face_bc=(0, 0, 0, 0, 3, 3), storage="m32"), "moment storage"),
+           (dict(face_bc=(0, 0, 0, 0, 4, 4)), "unknown rule")]
+    for kw, msg in bad:
+        cfg = dict(base)
+        cfg.update(kw)
+        assert required(**cfg) == 0, kw
+        assert msg in lbm.lbm_last_error(), (kw, lbm.lbm_last_error())
+
+
+def test_slab_split():
+    from paper_1710_02065_amd.slabs import split
+    assert split(10, 3) == [4, 3, 3]
+    assert split(256, 8) == [32] * 8
+    assert split(5, 5) == [1] * 5
+    for n, k in [(4, 5), (4, 0)]:
+        with pytest.raises(ValueError):
+            split(n, k)

@@ -85,8 +85,11 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_F16S = 3, LBM_M64 = 4, LBM_M3
  *             axes), read from this context's receive buffer; each step
  *             writes the populations leaving through the face into the send
  *             buffer (lbm_halo_buffers, lbm_halo_exchange).  The stepping
- *             equals that of the undivided grid: same operations, same
- *             values.  Conditions: no refinement, no absorbing-layer width
+ *             is that of the undivided grid, bitwise when both run the same
+ *             sweep path (a subdomain whose other faces are periodic or
+ *             cuts, without mask or layer, takes the periodic path; give it
+ *             an all-FLUID mask to match an undivided grid on the general
+ *             path).  Conditions: no refinement, no absorbing-layer width
  *             on the face, no SOLID cell in the face plane (both subdomains'
  *             face planes, each checked by its own lbm_init), one step per
  *             lbm_step call.  Inlet noise is drawn from the subdomain's own

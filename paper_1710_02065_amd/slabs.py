@@ -44,6 +44,11 @@ class Slabs:
         if sponge_width[lo] or sponge_width[hi]:
             raise ValueError("no face absorbing layer along the cut axis (use a per-cell layer)")
         self.ring = face_bc[lo] == lbm.LBM_PERIODIC
+        # the undivided grid runs the periodic sweep path only when every face
+        # is periodic, there is no layer and no mask; otherwise each slab is
+        # given a mask (all FLUID if none) so that it runs the general path too
+        self.general = (any(f != lbm.LBM_PERIODIC for f in face_bc)
+                        or kw.get("chi_max", 0.0) > 0)
         self.sizes = split(shape[ax], k)
         self.plane = shape[0] * (shape[1] if d3 else 1)
         kw.setdefault("stream", torch.cuda.current_stream().cuda_stream)
@@ -81,6 +86,8 @@ class Slabs:
 
         rho, u, pi_neq = dev_(rho, t.float64), dev_(u, t.float64), dev_(pi_neq, t.float64)
         mask = dev_(mask, t.uint8)
+        if mask is None and self.general:
+            mask = t.zeros(self.ncell, dtype=t.uint8, device=dev)
         if u is not None:
             u = u.reshape(-1, self.ncell)
         if pi_neq is not None:

@@ -206,11 +206,14 @@ __device__ __forceinline__ void record_moments(const SweepArgs<S>& a,
     for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
   }
   if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
-    a.recf[c] = mo.drho;
+    // ten contiguous values per node: the IMPORT filter reads a node's
+    // stress components together
+    typename S::R* rc = a.recf + (uint64_t)c * 10;
+    rc[0] = mo.drho;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.recf[(uint64_t)(1 + k) * a.ncell + c] = mo.u[k];
+    for (int k = 0; k < 3; ++k) rc[1 + k] = mo.u[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a.recf[(uint64_t)(4 + k) * a.ncell + c] = mo.a2[k];
+    for (int k = 0; k < 6; ++k) rc[4 + k] = mo.a2[k];
   }
 }
 
@@ -890,7 +893,6 @@ __global__ void k_import(ImportArgs ia) {
                         (int32_t)(cc / (ia.cnx * ia.cny))};
   int32_t kc[3];
   for (int ax = 0; ax < 3; ++ax) kc[ax] = ax < L::D ? 2 * (p[ax] - ia.lo[ax]) : 0;
-  const uint64_t fn = (uint64_t)ia.fnx * ia.fny * ia.fnz;
   const R* M = (const R*)ia.recf;
   const R w1[3] = {(R)0.25, (R)0.5, (R)0.25};
   const int oz = L::D == 3 ? 1 : 0;
@@ -901,11 +903,11 @@ __global__ void k_import(ImportArgs ia) {
         const uint64_t c = ((uint64_t)(kc[2] + o2) * ia.fny + (uint64_t)(kc[1] + o1)) * ia.fnx +
                            (uint64_t)(kc[0] + o0);
         const R w = w1[o0 + 1] * w1[o1 + 1] * (oz ? w1[o2 + 1] : (R)1);
-        for (int q = 0; q < 6; ++q) acc[q] += w * M[(uint64_t)(4 + q) * fn + c];
+        for (int q = 0; q < 6; ++q) acc[q] += w * M[c * 10 + 4 + q];
       }
   const uint64_t c0 = ((uint64_t)kc[2] * ia.fny + (uint64_t)kc[1]) * ia.fnx + (uint64_t)kc[0];
-  const R drho_c = M[c0];
-  const R u_c[3] = {M[fn + c0], M[2 * fn + c0], L::D == 3 ? M[3 * fn + c0] : (R)0};
+  const R drho_c = M[c0 * 10];
+  const R u_c[3] = {M[c0 * 10 + 1], M[c0 * 10 + 2], L::D == 3 ? M[c0 * 10 + 3] : (R)0};
   for (int q = 0; q < 6; ++q) acc[q] *= (R)ia.alpha;
   R out[L::Q];
   rebuild_state<L, R>(drho_c, (R)ia.rho0, u_c, acc, (R)ia.omega1, out);

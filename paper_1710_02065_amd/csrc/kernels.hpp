@@ -174,8 +174,9 @@ struct SweepArgs {
   uint32_t rec_n;
   int32_t box_lo[3], box_hi[3];
   // refinement, child side: pre-collision moments of the nodes in the band
-  // the parent's IMPORT nodes filter are recorded into recf (10 components,
-  // SoA over all ncell nodes of this level); nullptr disables it
+  // the parent's IMPORT nodes filter are recorded into recf (10 contiguous
+  // components per node, indexed by the node over all ncell nodes of this
+  // level); nullptr disables it
   R* recf;
   // absorbing layer given per cell: chi, rho_ref, u_ref (5 x ncell), read
   // for cells flagged kFieldSponge; nullptr: none

@@ -127,7 +127,7 @@ struct RingArgs {
 };
 
 // IMPORT nodes of a parent level rebuilt from the child's recorded
-// pre-collision moments (band record, 10 components over the child's nodes).
+// pre-collision moments (band record: 10 contiguous components per child node).
 struct ImportArgs {
   const uint32_t* list;
   uint32_t n;

@@ -199,11 +199,13 @@ __device__ __forceinline__ void record_moments(const SweepArgs<S>& a,
   const int64_t r =
       a.rec ? record_index<L::D>(a.rec_off, a.rec_dim, a.box_lo, a.box_hi, x, y, z) : -1;
   if (r >= 0) {
-    a.rec[r] = mo.drho;
+    // ten contiguous values per node (read together by the RING fill)
+    typename S::R* rr = a.rec + (uint64_t)r * 10;
+    rr[0] = mo.drho;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.rec[(uint64_t)(1 + k) * a.rec_n + r] = mo.u[k];
+    for (int k = 0; k < 3; ++k) rr[1 + k] = mo.u[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a.rec[(uint64_t)(4 + k) * a.rec_n + r] = mo.a2[k];
+    for (int k = 0; k < 6; ++k) rr[4 + k] = mo.a2[k];
   }
   if (a.recf && in_import_band<L::D>(x, y, z, a.nx, a.ny, a.nz)) {
     // ten contiguous values per node: the IMPORT filter reads a node's
@@ -797,8 +799,8 @@ __global__ void k_record_fields(RecordFieldsArgs a) {
   R* ra = (R*)a.rec_a;
   R* rb = (R*)a.rec_b;
   for (int k = 0; k < 10; ++k) {
-    ra[(uint64_t)k * a.rec_n + r] = v[k];
-    rb[(uint64_t)k * a.rec_n + r] = v[k];
+    ra[(uint64_t)r * 10 + k] = v[k];
+    rb[(uint64_t)r * 10 + k] = v[k];
   }
 }
 
@@ -861,7 +863,7 @@ __global__ void k_ring(RingArgs a) {
             (uint64_t)(pts[0][i0] - a.rec_off[0]);
         const R w = (R)wts[0][i0] * (R)wts[1][i1] * (R)wts[2][i2];
         for (int q = 0; q < 10; ++q) {
-          const uint64_t o = (uint64_t)q * a.rec_n + r;
+          const uint64_t o = r * 10 + (uint64_t)q;
           m[q] += w * (wa * Ma[o] + wb * Mb[o]);
         }
       }

@@ -166,8 +166,9 @@ struct SweepArgs {
   uint32_t lstride;      // inlet-noise counter blocks per time index
   uint32_t ntiles;
   // refinement: pre-collision moments of the coarse nodes on the patch
-  // boundary planes are recorded into rec (10 components, SoA over the
-  // record box [rec_off, rec_off + rec_dim)); rec == nullptr disables it
+  // boundary planes are recorded into rec (10 contiguous components per
+  // node of the record box [rec_off, rec_off + rec_dim)); rec == nullptr
+  // disables it
   R* rec;
   int32_t rec_off[3];
   uint32_t rec_dim[3];

@@ -73,6 +73,24 @@ def test_periodic_ring_matches_undivided_bitwise(storage, k, general):
     sl.close()
 
 
+@pytest.mark.parametrize("q,shape,k", [(9, (70, 45, 1), 3), (9, (33, 2, 1), 2),
+                                       (27, (22, 14, 15), 3), (27, (9, 5, 2), 2)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_periodic_path_rings_d2q9_d3q27_bitwise(q, shape, k, storage):
+    """Rings on the periodic path for D2Q9 (cut along y, three crossing
+    directions) and D3Q27 (nine), including one-plane slabs, against the
+    undivided periodic grid."""
+    case = dict(name="ring%d" % q, q=q, shape=shape, tau=0.56)
+    fields = W.random_state(shape, seed=94 + q + k, d=2 if q == 9 else 3)
+    log("slab ring q=%d %s k=%d storage=%s" % (q, shape, k, storage))
+    ref = undivided(case, storage, fields=fields, steps=7)
+    sl = split_run(case, k, storage, fields=fields, steps=7)
+    assert not sl.general
+    assert same(sl.populations(), ref.populations())
+    sl.sync()
+    sl.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 def test_channel_split_across_walls_bitwise(storage):
     """D2Q9 cylinder channel cut along y into three slabs: free-slip walls

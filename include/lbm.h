@@ -189,8 +189,8 @@ typedef struct lbm_ctx lbm_ctx;
 void lbm_config_init(lbm_config* cfg);
 
 /* Device bytes lbm_create would allocate for this configuration (both
- * population buffers of every level, mask, interface buffers).  0 on an
- * invalid configuration (see lbm_last_error). */
+ * population buffers of every level, mask, interface buffers, halo buffers
+ * of LBM_HALO faces).  0 on an invalid configuration (see lbm_last_error). */
 size_t lbm_required_bytes(const lbm_config* cfg);
 
 /* Validate the configuration and create a context.  Rejects: tau <= 1/2

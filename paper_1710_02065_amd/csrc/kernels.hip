@@ -575,7 +575,9 @@ __global__ void k_set_pop(PopArgs a) {
 // ------------------------------------------------------------------------
 // Persistent batched sweep (serving): a fixed grid walks the (job, tile)
 // work list of every resident context; the step index comes from device
-// memory, so a captured sequence of launches replays for any job table.
+// memory plus the launch's offset s_off (a captured sequence of launches
+// carries offsets 0, 1, ... and advances the base once at its end), so the
+// sequence replays for any job table.
 // Each cell runs the same sweep_cell instantiation as a solo launch of its
 // context, so results are bitwise those of lbm_step.
 // ------------------------------------------------------------------------
@@ -597,8 +599,9 @@ __device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_
 template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
     __attribute__((amdgpu_waves_per_eu(SweepWaves<L, S, kGeneral>::value)))
-    k_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr) {
-  const int32_t s = hdr->step;
+    k_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr,
+            int32_t s_off) {
+  const int32_t s = hdr->step + s_off;
   const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
   for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
     // last job whose first tile is <= tile
@@ -615,8 +618,8 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-__global__ void k_batch_bump(BatchHeader* hdr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->step += 1;
+__global__ void k_batch_bump(BatchHeader* hdr, int32_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->step += by;
 }
 
 // Flag bits of every cell's mask byte: kNearSolid if a neighbour reached
@@ -1074,20 +1077,21 @@ void fill_fastdiv(uint32_t d, uint32_t out[3]) {
 
 // Batch kernel variants: variant = lattice code * 16 + storage * 2 + general.
 template <class L, class S, bool G>
-static hipError_t batch_t(bool query, const BatchJob* jobs, BatchHeader* hdr, int block,
-                          int grid, hipStream_t st, int* per) {
+static hipError_t batch_t(bool query, const BatchJob* jobs, BatchHeader* hdr, int32_t s_off,
+                          int block, int grid, hipStream_t st, int* per) {
   if (query)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_batch<L, S, G>, block, 0);
-  hipLaunchKernelGGL((k_batch<L, S, G>), dim3(grid), dim3(block), 0, st, jobs, hdr);
+  hipLaunchKernelGGL((k_batch<L, S, G>), dim3(grid), dim3(block), 0, st, jobs, hdr, s_off);
   return hipGetLastError();
 }
 
 template <class L>
 static hipError_t batch_l(int storage, bool general, bool query, const BatchJob* jobs,
-                          BatchHeader* hdr, int block, int grid, hipStream_t st, int* per) {
+                          BatchHeader* hdr, int32_t s_off, int block, int grid, hipStream_t st,
+                          int* per) {
 #define HRLBM_BATCH(S)                                                            \
-  return general ? batch_t<L, S, true>(query, jobs, hdr, block, grid, st, per)    \
-                 : batch_t<L, S, false>(query, jobs, hdr, block, grid, st, per);
+  return general ? batch_t<L, S, true>(query, jobs, hdr, s_off, block, grid, st, per)    \
+                 : batch_t<L, S, false>(query, jobs, hdr, s_off, block, grid, st, per);
   switch (storage) {
     case 0: HRLBM_BATCH(StoreF64)
     case 1: HRLBM_BATCH(StoreF32)
@@ -1099,41 +1103,41 @@ static hipError_t batch_l(int storage, bool general, bool query, const BatchJob*
 }
 
 static hipError_t batch_dispatch(int variant, bool query, const BatchJob* jobs,
-                                 BatchHeader* hdr, int block, int grid, hipStream_t st,
-                                 int* per) {
+                                 BatchHeader* hdr, int32_t s_off, int block, int grid,
+                                 hipStream_t st, int* per) {
   const int lattice = variant / 16, storage = (variant / 2) % 8;
   const bool general = variant & 1;
   switch (lattice) {
-    case 9: return batch_l<Lattice<9>>(storage, general, query, jobs, hdr, block, grid, st, per);
-    case 19: return batch_l<Lattice<19>>(storage, general, query, jobs, hdr, block, grid, st, per);
-    case 27: return batch_l<Lattice<27>>(storage, general, query, jobs, hdr, block, grid, st, per);
+    case 9: return batch_l<Lattice<9>>(storage, general, query, jobs, hdr, s_off, block, grid, st, per);
+    case 19: return batch_l<Lattice<19>>(storage, general, query, jobs, hdr, s_off, block, grid, st, per);
+    case 27: return batch_l<Lattice<27>>(storage, general, query, jobs, hdr, s_off, block, grid, st, per);
     case kFullOrderCode + 9:
-      return batch_l<Lattice<9, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
+      return batch_l<Lattice<9, true>>(storage, general, query, jobs, hdr, s_off, block, grid, st, per);
     case kFullOrderCode + 27:
-      return batch_l<Lattice<27, true>>(storage, general, query, jobs, hdr, block, grid, st, per);
+      return batch_l<Lattice<27, true>>(storage, general, query, jobs, hdr, s_off, block, grid, st, per);
     case kBgkCode + 9:
-      return batch_l<Lattice<9, false, kCollBGK>>(storage, general, query, jobs, hdr, block, grid,
+      return batch_l<Lattice<9, false, kCollBGK>>(storage, general, query, jobs, hdr, s_off, block, grid,
                                                   st, per);
     case kBgkCode + 19:
-      return batch_l<Lattice<19, false, kCollBGK>>(storage, general, query, jobs, hdr, block,
+      return batch_l<Lattice<19, false, kCollBGK>>(storage, general, query, jobs, hdr, s_off, block,
                                                    grid, st, per);
     case kBgkCode + 27:
-      return batch_l<Lattice<27, false, kCollBGK>>(storage, general, query, jobs, hdr, block,
+      return batch_l<Lattice<27, false, kCollBGK>>(storage, general, query, jobs, hdr, s_off, block,
                                                    grid, st, per);
     case kMrtCode + 9:
-      return batch_l<Lattice<9, false, kCollMRT>>(storage, general, query, jobs, hdr, block, grid,
+      return batch_l<Lattice<9, false, kCollMRT>>(storage, general, query, jobs, hdr, s_off, block, grid,
                                                   st, per);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int block,
-                        int grid, hipStream_t st) {
-  return batch_dispatch(variant, false, jobs, hdr, block, grid, st, nullptr);
+hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int32_t s_off,
+                        int block, int grid, hipStream_t st) {
+  return batch_dispatch(variant, false, jobs, hdr, s_off, block, grid, st, nullptr);
 }
 
-hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_bump, dim3(1), dim3(64), 0, st, hdr);
+hipError_t launch_batch_bump(BatchHeader* hdr, int32_t by, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_bump, dim3(1), dim3(64), 0, st, hdr, by);
   return hipGetLastError();
 }
 
@@ -1142,7 +1146,7 @@ int batch_grid(int variant, int block) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (batch_dispatch(variant, true, nullptr, nullptr, block, 0, nullptr, &per) != hipSuccess ||
+  if (batch_dispatch(variant, true, nullptr, nullptr, 0, block, 0, nullptr, &per) != hipSuccess ||
       per < 1)
     per = 1;
   return cus * per;

@@ -225,7 +225,7 @@ struct BatchJob {
 struct BatchHeader {
   uint32_t njobs;
   uint32_t total_tiles;
-  int32_t step;  // current step index s within the batch
+  int32_t step;  // base of the step index s within the batch (plus the launch's offset)
   int32_t pad;
 };
 
@@ -233,9 +233,11 @@ hipError_t launch_sweep(int lattice, int storage, const SweepHost& h, int block,
                         hipStream_t st);
 // persistent batched sweep: grid of `grid` workgroups of `block` threads
 // variant = lattice code * 16 + storage * 2 + (general path ? 1 : 0)
-hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int block,
-                        int grid, hipStream_t st);
-hipError_t launch_batch_bump(BatchHeader* hdr, hipStream_t st);
+// s_off: offset added to the device-side step index for this launch
+hipError_t launch_batch(int variant, const BatchJob* jobs, BatchHeader* hdr, int32_t s_off,
+                        int block, int grid, hipStream_t st);
+// advance the device-side step index by `by`
+hipError_t launch_batch_bump(BatchHeader* hdr, int32_t by, hipStream_t st);
 int batch_grid(int variant, int block);  // resident workgroups on the device
 void fill_fastdiv(uint32_t d, uint32_t out[3]);
 hipError_t launch_init(int lattice, int storage, const InitArgs& a, uint32_t n,

@@ -98,10 +98,10 @@ static int graph_for(BatchRunner* r, int variant, int block, int grid, GraphEntr
     GraphEntry g{};
     hipError_t e = hipStreamBeginCapture(r->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "batch capture begin");
-    for (int k = 0; k < kBatchGraphSteps && e == hipSuccess; ++k) {
-      e = launch_batch(variant, r->d_jobs, r->d_hdr, block, grid, r->capture);
-      if (e == hipSuccess) e = launch_batch_bump(r->d_hdr, r->capture);
-    }
+    // steps base + 0 ... base + kBatchGraphSteps - 1, then base += kBatchGraphSteps
+    for (int k = 0; k < kBatchGraphSteps && e == hipSuccess; ++k)
+      e = launch_batch(variant, r->d_jobs, r->d_hdr, (int32_t)k, block, grid, r->capture);
+    if (e == hipSuccess) e = launch_batch_bump(r->d_hdr, (int32_t)kBatchGraphSteps, r->capture);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(r->capture, &graph);
     if (e != hipSuccess) return hip_error(e, "batch launch during capture");
@@ -180,9 +180,12 @@ static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64
       if (e != hipSuccess) return hip_error(e, "batch graph launch");
     }
   }
+  // the graphs advanced the device-side base to `done`: the remaining
+  // steps pass their offset from it
+  const int64_t base = done;
   for (; done < max_steps; ++done) {
-    e = launch_batch(variant, r->d_jobs, r->d_hdr, block, grid, r->stream);
-    if (e == hipSuccess) e = launch_batch_bump(r->d_hdr, r->stream);
+    e = launch_batch(variant, r->d_jobs, r->d_hdr, (int32_t)(done - base), block, grid,
+                     r->stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
   for (auto& kv : grp) {

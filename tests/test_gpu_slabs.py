@@ -146,6 +146,31 @@ def test_open_ends_split_bitwise(storage):
     sl.close()
 
 
+@pytest.mark.parametrize("q,flags,faces,shape", [
+    (9, lbm.LBM_MRT, (0, 0, 0, 0, 0, 0), (48, 30, 1)),
+    (9, lbm.LBM_BGK, (2, 2, 1, 1, 0, 0), (48, 30, 1)),
+    (19, lbm.LBM_BGK, (0, 0, 0, 0, 2, 1), (20, 12, 15)),
+    (27, lbm.LBM_BGK, (1, 1, 0, 0, 0, 0), (14, 10, 12))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_comparator_collisions_split_bitwise(q, flags, faces, shape, storage):
+    """The comparator collisions (LBM-BGK, D2Q9 LBM-MRT) across cuts: the
+    halo pull is shared, so split runs stay bitwise the undivided ones."""
+    case = dict(name="comparator", q=q, shape=shape, tau=0.6, face_bc=faces)
+    fields = W.random_state(shape, seed=95 + q, d=2 if q == 9 else 3)
+    n = int(np.prod(shape))
+    mask = np.zeros(n, np.uint8)
+    log("slab comparator q=%d flags=%d storage=%s" % (q, flags, storage))
+    ref = gpu_sim(case, storage, flags=flags)
+    ref.init(*fields, mask)
+    ref.step(6)
+    sl = Slabs(3, shape, lattice=q, tau=0.6, storage=storage, face_bc=faces, flags=flags)
+    sl.init(*fields, mask)
+    sl.step(6)
+    assert same(sl.populations(), ref.populations())
+    sl.sync()
+    sl.close()
+
+
 def test_split_run_matches_oracle_f64():
     """The split FP64 run against the undivided oracle grid."""
     case = dict(name="oracle", q=19, shape=(18, 11, 14), tau=0.57, face_bc=(1, 1, 0, 0, 2, 2),

@@ -263,6 +263,29 @@ def test_checkpoint_resume_across_cuts():
     b.sync()
 
 
+def test_full_size_channel_in_three_slabs_bitwise():
+    """The 2048 x 1024 cylinder channel (D = 100 at (400, 512), Ma 0.2, Re
+    150, inlet column, outflow with a 128-column layer, free-slip walls) cut
+    along y into three slabs whose cuts miss the disc, FP32, without inlet
+    noise: equal to the undivided channel after 50 steps."""
+    nx, ny, D = 2048, 1024, 100
+    U = 0.2 * 3 ** -0.5
+    case = dict(name="channel-full", q=9, shape=(nx, ny, 1), tau=0.5 + 3 * U * D / 150, ma=0.2,
+                face_bc=(2, 2, 1, 1, 0, 0), sponge_width=(0, 128, 0, 0, 0, 0), chi_max=0.2,
+                u_ref=(U, 0.0, 0.0))
+    mask = W.cylinder_mask(nx, ny, D, 400, 512)
+    rho, u = W.uniform_perturbed((nx, ny, 1), U, (1, 0, 0), seed=2, rel_noise=1e-4, d=2)
+    log("slab full-size channel")
+    sl = split_run(case, 3, "f32", mask=mask, fields=(rho, u, None), steps=50)
+    assert sl.sizes == [342, 341, 341]
+    got = sl.populations()
+    sl.sync()
+    sl.close()
+    ref = undivided(case, "f32", mask=mask, fields=(rho, u, None), steps=50)
+    assert same(got, ref.populations())
+    ref.sync()
+
+
 def test_headline_grid_in_eight_slabs_bitwise():
     """D3Q19 256^3 Taylor-Green + pulse (FP32) as eight 256x256x32 slabs,
     one GPU's share each when the grid is spread over eight GPUs: equal to

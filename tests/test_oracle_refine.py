@@ -205,3 +205,61 @@ def test_shear_wave_across_interface(q):
     assert ec < 1e-3 and ef < 1e-3, (ec, ef)
     # the coupling is not mass conservative; the drift is reported, bounded
     assert drift < 1e-6
+
+
+@pytest.mark.parametrize("q,shape,lo,hi", [
+    (9, (40, 32, 1), (10, 8, 0), (26, 20, 0)),
+    (19, (20, 18, 16), (5, 5, 5), (13, 12, 11)),
+])
+def test_import_filter_weights_from_a_quadratic_stress(q, shape, lo, hi):
+    """Pins the decimation weights of Sec. II.B (eq. couplingCF): on a
+    field quadratic in the fine index k, the tensor filter (1/4, 1/2, 1/4)
+    adds exactly its second moment, sum_o w(o) o^2 = 1/2, per axis in which
+    the field is curved, and keeps the mixed product k_x k_y (odd moments
+    vanish).  Any other normalised symmetric three-point kernel adds a
+    different constant: (1/3, 1/3, 1/3) adds 2/3."""
+    tau = 0.7
+    R = make(q, shape, lo, hi, tau=tau)
+    d = 2 if q == 9 else 3
+    fx, fy, fz = fine_coords(R)
+    kx, ky = 2.0 * (fx - lo[0]), 2.0 * (fy - lo[1])
+    kz = 2.0 * (fz - lo[2]) if d == 3 else 0.0 * fz
+    Nf = R.fine.N
+    s = 1e-6
+    rho_f = np.ones(Nf)
+    u_f = np.zeros((3, Nf))
+    a2_f = np.zeros((6, Nf))
+    a2_f[0] = s * (kx * kx + 2.0 * ky * ky - kz * kz)   # xx
+    a2_f[1] = s * (3.0 * kx * ky - ky * ky)             # yy
+    a2_f[3] = s * kx * ky                               # xy
+    if d == 3:
+        a2_f[2] = s * (kz * kz + kx)                    # zz
+        a2_f[4] = s * (kx * kz - 0.5 * kz * kz)         # xz
+    lib().ora_ref_import(C.byref(R.R), _u8p(R.crole), _dp(rho_f), _dp(u_f), _dp(a2_f),
+                         _dp(R.coarse.f))
+    X, Y, Z = coarse_coords(R)
+    imp = R.crole == O.IMPORT
+    assert imp.sum() > 0
+    # the coincident fine node of coarse node X is k = 2 (X - lo)
+    Kx, Ky = 2.0 * (X - lo[0]), 2.0 * (Y - lo[1])
+    Kz = 2.0 * (Z - lo[2]) if d == 3 else 0.0 * Z
+    half = 0.5  # second moment of (1/4, 1/2, 1/4)
+    want = np.zeros((6, R.coarse.N))
+    want[0] = s * ((Kx * Kx + half) + 2.0 * (Ky * Ky + half) - (Kz * Kz + (half if d == 3 else 0)))
+    want[1] = s * (3.0 * Kx * Ky - (Ky * Ky + half))
+    want[3] = s * Kx * Ky
+    if d == 3:
+        want[2] = s * ((Kz * Kz + half) + Kx)
+        want[4] = s * (Kx * Kz - 0.5 * (Kz * Kz + half))
+    xi, _, _ = O.lattice(q)
+    f = R.coarse.f[:, imp]
+    rho = f.sum(0)
+    j = xi.T.astype(float) @ f
+    u = j / rho
+    Pi = np.einsum("ia,ib,in->abn", xi.astype(float), xi.astype(float), f)
+    scale = (1.0 - 1.0 / tau) * 2.0 * tau / R.fine.g.tau
+    comps = [(0, 0, 0), (1, 1, 1), (3, 0, 1)] + ([(2, 2, 2), (4, 0, 2)] if d == 3 else [])
+    for k, a, b in comps:
+        a2 = Pi[a, b] - rho * u[a] * u[b] - (CS2 * rho if a == b else 0.0)
+        np.testing.assert_allclose(a2, scale * want[k][imp], rtol=0, atol=1e-14,
+                                   err_msg="component %d" % k)

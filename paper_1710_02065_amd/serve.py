@@ -3,7 +3,8 @@
 Jobs (2D D2Q9 cylinder-in-channel or acoustic-pulse lattices of uneven
 sizes) arrive over time.  The server keeps every admitted job's populations
 resident in HBM, admits queued jobs in arrival order whenever their device
-footprint (lbm_required_bytes) fits the remaining budget, and advances all
+footprint (lbm_required_bytes) fits the remaining budget (a job that does
+not fit is not overtaken by later jobs that would delay it), and advances all
 resident jobs together: each quantum is one lbm_step_batch call, i.e. one
 persistent batched launch sequence (replayed as hipGraphs) over the (job,
 tile) work list of every resident lattice.  Jobs that arrive while others
@@ -91,14 +92,24 @@ class Server:
             now = be.now() - t0
             while pending and pending[0].job["arrival"] <= now:
                 queue.append(pending.pop(0))
-            # admit in arrival order every queued job that fits
+            # Admit in arrival order.  The first queued job that does not fit
+            # holds a reservation: a later job is admitted past it only if it
+            # fits now and ends no later than the reserved job could start,
+            # so the reserved job's wait is bounded by the work resident when
+            # it reached the head of the queue, whatever arrives after it.
+            wait = None  # steps until the reserved job fits
             for r in list(queue):
-                if used + r.need <= self.budget:
-                    r.handle = be.start(r.job)
-                    r.admitted = be.now() - t0
-                    used += r.need
-                    queue.remove(r)
-                    active.append(r)
+                if used + r.need > self.budget:
+                    if wait is None:
+                        wait = self._steps_until_fits(active, used, r.need)
+                    continue
+                if wait is not None and r.job["steps"] > wait:
+                    continue
+                r.handle = be.start(r.job)
+                r.admitted = be.now() - t0
+                used += r.need
+                queue.remove(r)
+                active.append(r)
             st.peak_bytes = max(st.peak_bytes, used)
             if not active:
                 if pending:
@@ -124,6 +135,18 @@ class Server:
             st.makespan = max(r.finished for r in done) - min(r.job["arrival"] for r in done)
         self.records = done
         return st
+
+
+    def _steps_until_fits(self, active, used, need):
+        """Steps after which a job of `need` bytes fits: every resident job
+        advances by the same steps per batched call (up to its remaining
+        steps), so they finish in the order of their remaining steps."""
+        free = self.budget - used
+        for r in sorted(active, key=lambda r: r.remaining):
+            free += r.need
+            if free >= need:
+                return r.remaining
+        return 0
 
 
 class FakeBackend:
@@ -260,9 +283,15 @@ class GpuBackend:
         lbm.lbm_moments(h["ctx"], 0, rho, None)
         out = dict(id=job["id"], rho_mean=None, pops=None)
         if self.keep:
+            # final populations and density, and the initial fields the job
+            # started from (host copies), for checking a job's result
             pops = t.empty(9, n, dtype=t.float64, device=self.dev)
             lbm.lbm_get_populations(h["ctx"], 0, pops)
             out["pops"] = pops.cpu()
+            out["rho"] = rho.cpu()
+            r0, u0, m0 = h["keep"]
+            out["init"] = (r0.cpu().numpy(), u0.cpu().numpy(),
+                           None if m0 is None else m0.cpu().numpy())
         out["rho_mean"] = float(rho.mean().item())
         lbm.lbm_sync(h["ctx"])
         lbm.lbm_destroy(h["ctx"])

@@ -54,6 +54,41 @@ def test_admission_in_arrival_order_when_everything_fits():
         assert r.finished - r.job["arrival"] >= be.cells(r.job) * r.job["steps"] / 1e9 - 1e-12
 
 
+def _stream_with_big_job(n_small, big_at=5):
+    """Short 64x64 jobs arriving faster than they finish, and one 256x256
+    job (the whole budget) arriving as the sixth."""
+    js = []
+    t = 0.0
+    for k in range(n_small + 1):
+        big = k == big_at
+        js.append(dict(id=k, kind="pulse", nx=256 if big else 64, ny=256 if big else 64,
+                       ma=0.1, steps=300 if big else 200, storage="f32", seed=k, arrival=t))
+        t += 2e-4
+    return js
+
+
+@pytest.mark.parametrize("n_small", [40, 400])
+def test_reserved_head_job_is_not_starved(n_small):
+    """Tight budget: the large job needs all of it.  Later small jobs are
+    admitted past it only if they end before it can start, so its queueing
+    delay is bounded by the work resident when it reached the head of the
+    queue (at most one small job's steps), independent of how long the
+    stream of small jobs lasts."""
+    js = _stream_with_big_job(n_small)
+    be = serve.FakeBackend(mlups=2000.0, launch_overhead=1e-4)
+    big = max(js, key=lambda j: j["nx"] * j["ny"])
+    budget = be.required_bytes(big)
+    srv = serve.Server(be, budget, quantum=50)
+    st = srv.run(js)
+    assert len(st.latencies) == len(js)
+    assert be.max_live_bytes <= budget
+    rec = {r.job["id"]: r for r in srv.records}[big["id"]]
+    small_steps = max(j["steps"] for j in js if j is not big)
+    calls = -(-small_steps // 50)  # batched calls until the resident jobs end
+    per_call = 1e-4 + (budget / be.bpc) * 50 / (be.mlups * 1e6)  # a full budget's quantum
+    assert rec.admitted - big["arrival"] <= calls * per_call + 1e-12
+
+
 def test_job_larger_than_budget_is_rejected():
     js = jobs(n=3)
     be = serve.FakeBackend()

@@ -325,6 +325,25 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
  * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */
 int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
 
+/* Largest n lbm_step_batch_noalloc accepts. */
+#define LBM_NOALLOC_MAX_JOBS 256
+
+/* lbm_step_batch for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same contexts, the same kernels and bitwise the same results as
+ * lbm_step_batch, with no hipMalloc, hipFree, host staging allocation or
+ * graph instantiation.  The job tables live in a fixed device array of
+ * static storage (about 110 KB: LBM_NOALLOC_MAX_JOBS batch headers and
+ * jobs) that each device the library runs on holds until the process ends;
+ * they are uploaded through kernel arguments and every step is its own
+ * batch launch.  The caller still provides the contexts (whose memory
+ * lbm_init or lbm_bind_memory set up beforehand).  Errors: LBM_EINVAL if
+ * n > LBM_NOALLOC_MAX_JOBS or a step count exceeds 2^31 - 1, otherwise as
+ * lbm_step_batch.  Every call on one device shares that device's tables and
+ * rewrites them: calls on one stream are ordered, but calls that overlap on
+ * one device (other streams or threads) race. */
+int lbm_step_batch_noalloc(lbm_ctx* const* ctxs, const int64_t* steps, int n);
+
 /* Time the sweep for each candidate workgroup size (64, 128, 256, 512,
  * 1024; for the moment storages the same values select block / 16 planes
  * per workgroup) on this context's current state (the state is restored

@@ -1,10 +1,12 @@
 // Serving entry points: batched stepping of many resident contexts through
-// the persistent batch kernel (with hipGraph replay of step sequences), and
-// the workgroup-size autotuner with its on-disk cache.
+// the persistent batch kernel (with hipGraph replay of step sequences), its
+// allocation-free variant, and the workgroup-size autotuner with its on-disk
+// cache.
 #include <hip/hip_runtime.h>
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -197,6 +199,153 @@ static int run_group(BatchRunner* r, const std::vector<std::pair<lbm_ctx*, int64
   return LBM_OK;
 }
 
+// ------------------------------------------------------- allocation-free --
+// lbm_step_batch_noalloc keeps its job tables in `scratch`, an array of
+// static storage that every device the library runs on holds until the
+// process ends: kNoAllocMaxJobs batch headers (one per group), then
+// kNoAllocMaxJobs jobs.  Host code never uses the array's name as an
+// address: the device address comes from hipGetSymbolAddress, once per
+// device, and is what the kernels receive.
+static constexpr int kNoAllocMaxJobs = LBM_NOALLOC_MAX_JOBS;
+static constexpr size_t kNoAllocHdrBytes = kNoAllocMaxJobs * sizeof(BatchHeader);
+static constexpr size_t kNoAllocBytes = kNoAllocHdrBytes + kNoAllocMaxJobs * sizeof(BatchJob);
+static_assert(kNoAllocHdrBytes % 256 == 0, "job table alignment");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch[kScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+static int scratch_for(int device, unsigned char** out) {
+  if (device < 0 || device >= kScratchDevices)
+    return set_error(LBM_EINVAL, "device %d beyond the %d the allocation-free tables cover",
+                     device, kScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "address of the allocation-free job tables");
+    if (!p) return set_error(LBM_EDEVICE, "allocation-free job tables have no address");
+    g_scratch[device] = (unsigned char*)p;
+  }
+  *out = g_scratch[device];
+  return LBM_OK;
+}
+
+// Jobs written per table launch: the chunk travels as the kernel argument.
+static constexpr int kTableChunk = 2;
+struct TableChunk {
+  BatchHeader hdr;     // the group's header, written with the first chunk
+  uint32_t count;      // jobs in this chunk
+  uint32_t write_hdr;
+  BatchJob jobs[kTableChunk];
+};
+
+// One thread copies the chunk from its kernel argument into the tables
+// (plain global stores); the batch launches that follow on the same stream
+// read them.
+__global__ void k_write_table(TableChunk c, BatchHeader* hdr, BatchJob* jobs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+#pragma unroll
+  for (int k = 0; k < kTableChunk; ++k)
+    if ((uint32_t)k < c.count) jobs[k] = c.jobs[k];
+  if (c.write_hdr) *hdr = c.hdr;
+}
+
+// The batch table entry of a context (as run_group builds it).
+static void fill_job(BatchJob& J, lbm_ctx* c, int64_t steps, uint32_t tile_begin, int block) {
+  const Level& L = c->lv[0];
+  std::memset(&J, 0, sizeof J);
+  J.h = sweep_args(c, 0, L.cur, 0);
+  J.buf[0] = L.buf[0];
+  J.buf[1] = L.buf[1];
+  J.storage = c->cfg.storage;
+  J.cur0 = L.cur;
+  J.t0 = (uint64_t)L.t;
+  J.steps = steps;
+  J.tile_begin = tile_begin;
+  J.ntiles = (uint32_t)((L.N + block - 1) / block);
+  fill_fastdiv((uint32_t)L.nx, J.div_nx);
+  fill_fastdiv((uint32_t)L.ny, J.div_ny);
+}
+
+// One group (contexts order[0..count) sharing kernel variant and workgroup
+// size) through the tables at hdr / jobs: upload by kernel arguments, then
+// one batch launch per step with the step as the launch's offset (the
+// header's base stays 0).  No graphs, no host staging, no allocation.
+static int run_group_noalloc(lbm_ctx* const* ctxs, const int64_t* steps, const int* order,
+                             int count, BatchHeader* hdr, BatchJob* jobs) {
+  lbm_ctx* c0 = ctxs[order[0]];
+  const int variant = batch_variant(c0);
+  const int block = c0->block;
+  hipStream_t st = c0->stream;
+  int64_t max_steps = 0;
+  uint32_t tiles = 0;
+  for (int k = 0; k < count; ++k) {
+    const Level& L = ctxs[order[k]]->lv[0];
+    tiles += (uint32_t)((L.N + block - 1) / block);
+    max_steps = std::max(max_steps, steps[order[k]]);
+  }
+  if (max_steps == 0) return LBM_OK;
+  TableChunk chunk;
+  uint32_t tile_begin = 0;
+  for (int k0 = 0; k0 < count; k0 += kTableChunk) {
+    std::memset(&chunk, 0, sizeof chunk);
+    chunk.count = (uint32_t)std::min(kTableChunk, count - k0);
+    for (uint32_t k = 0; k < chunk.count; ++k) {
+      const int j = order[k0 + (int)k];
+      fill_job(chunk.jobs[k], ctxs[j], steps[j], tile_begin, block);
+      tile_begin += chunk.jobs[k].ntiles;
+    }
+    if (k0 == 0) {
+      chunk.write_hdr = 1;
+      chunk.hdr.njobs = (uint32_t)count;
+      chunk.hdr.total_tiles = tiles;
+      chunk.hdr.step = 0;
+    }
+    hipLaunchKernelGGL(k_write_table, dim3(1), dim3(64), 0, st, chunk, hdr, jobs + k0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "allocation-free table upload");
+  }
+  const int grid = batch_grid(variant, block);
+  if (grid <= 0) return set_error(LBM_EDEVICE, "batch occupancy query failed");
+  for (int64_t s = 0; s < max_steps; ++s) {
+    hipError_t e = launch_batch(variant, jobs, hdr, (int32_t)s, block, grid, st);
+    if (e != hipSuccess) return hip_error(e, "batch launch");
+  }
+  for (int k = 0; k < count; ++k) {
+    lbm_ctx* c = ctxs[order[k]];
+    const int64_t n = steps[order[k]];
+    c->lv[0].t += n;
+    c->lv[0].cur ^= (int)(n & 1);
+    c->t += n;
+  }
+  return LBM_OK;
+}
+
+// Checks shared by the batched entry points: every context initialised,
+// unrefined, population-stored, without halo faces, on one device and stream,
+// listed once, with a non-negative step count.
+static int check_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
+  for (int k = 0; k < n; ++k) {
+    int rc = check_ready(ctxs[k]);
+    if (rc != LBM_OK) return rc;
+    if (steps[k] < 0) return set_error(LBM_EINVAL, "negative step count for job %d", k);
+    if (ctxs[k]->nlevels > 1)
+      return set_error(LBM_EUNSUPPORTED, "refined contexts cannot be batched");
+    if (moment_storage(ctxs[k]->cfg.storage))
+      return set_error(LBM_EUNSUPPORTED, "moment-stored contexts cannot be batched");
+    if (has_halo(ctxs[k]->cfg))
+      return set_error(LBM_EUNSUPPORTED, "contexts with halo faces cannot be batched");
+    if (ctxs[k]->device != ctxs[0]->device || ctxs[k]->stream != ctxs[0]->stream)
+      return set_error(LBM_EINVAL, "batched contexts must share device and stream");
+    for (int m = 0; m < k; ++m)
+      if (ctxs[m] == ctxs[k]) return set_error(LBM_EINVAL, "context %d appears twice", k);
+  }
+  return LBM_OK;
+}
+
 // ---------------------------------------------------------------- tuning --
 static std::mutex g_tune_mu;
 
@@ -289,22 +438,9 @@ extern "C" {
 int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
   if (n < 0 || (n > 0 && (!ctxs || !steps))) return set_error(LBM_EINVAL, "batch arguments");
   if (n == 0) return LBM_OK;
-  for (int k = 0; k < n; ++k) {
-    int rc = check_ready(ctxs[k]);
-    if (rc != LBM_OK) return rc;
-    if (steps[k] < 0) return set_error(LBM_EINVAL, "negative step count for job %d", k);
-    if (ctxs[k]->nlevels > 1)
-      return set_error(LBM_EUNSUPPORTED, "refined contexts cannot be batched");
-    if (moment_storage(ctxs[k]->cfg.storage))
-      return set_error(LBM_EUNSUPPORTED, "moment-stored contexts cannot be batched");
-    if (has_halo(ctxs[k]->cfg))
-      return set_error(LBM_EUNSUPPORTED, "contexts with halo faces cannot be batched");
-    if (ctxs[k]->device != ctxs[0]->device || ctxs[k]->stream != ctxs[0]->stream)
-      return set_error(LBM_EINVAL, "batched contexts must share device and stream");
-    for (int m = 0; m < k; ++m)
-      if (ctxs[m] == ctxs[k]) return set_error(LBM_EINVAL, "context %d appears twice", k);
-  }
-  int rc = ensure_device(ctxs[0]);
+  int rc = check_batch(ctxs, steps, n);
+  if (rc != LBM_OK) return rc;
+  rc = ensure_device(ctxs[0]);
   if (rc != LBM_OK) return rc;
   std::lock_guard<std::mutex> lk(g_batch_mu);
   BatchRunner* r = nullptr;
@@ -318,6 +454,52 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
   for (auto& kv : groups) {
     rc = run_group(r, kv.second);
     if (rc != LBM_OK) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_step_batch_noalloc(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
+  if (n < 0 || (n > 0 && (!ctxs || !steps))) return set_error(LBM_EINVAL, "batch arguments");
+  if (n > kNoAllocMaxJobs)
+    return set_error(LBM_EINVAL, "%d contexts; the allocation-free batch takes at most %d", n,
+                     kNoAllocMaxJobs);
+  if (n == 0) return LBM_OK;
+  int rc = check_batch(ctxs, steps, n);
+  if (rc != LBM_OK) return rc;
+  for (int k = 0; k < n; ++k)
+    if (steps[k] > INT32_MAX)
+      return set_error(LBM_EINVAL, "step count of job %d beyond 2^31 - 1", k);
+  rc = ensure_device(ctxs[0]);
+  if (rc != LBM_OK) return rc;
+  unsigned char* base = nullptr;
+  rc = scratch_for(ctxs[0]->device, &base);
+  if (rc != LBM_OK) return rc;
+  BatchHeader* hdrs = (BatchHeader*)base;
+  BatchJob* jobs = (BatchJob*)(base + kNoAllocHdrBytes);
+  // group by (kernel variant, workgroup size), stable in the callers' order
+  int var[kNoAllocMaxJobs], order[kNoAllocMaxJobs];
+  for (int k = 0; k < n; ++k) {
+    var[k] = batch_variant(ctxs[k]);
+    order[k] = k;
+  }
+  auto before = [&](int a, int b) {
+    if (var[a] != var[b]) return var[a] < var[b];
+    if (ctxs[a]->block != ctxs[b]->block) return ctxs[a]->block < ctxs[b]->block;
+    return a < b;
+  };
+  for (int i = 1; i < n; ++i)
+    for (int j = i; j > 0 && before(order[j], order[j - 1]); --j) std::swap(order[j], order[j - 1]);
+  int groups = 0;
+  for (int g0 = 0; g0 < n;) {
+    int g1 = g0 + 1;
+    while (g1 < n && var[order[g1]] == var[order[g0]] &&
+           ctxs[order[g1]]->block == ctxs[order[g0]]->block)
+      ++g1;
+    // group `groups` uses header `groups` and the jobs from position g0 on
+    rc = run_group_noalloc(ctxs, steps, order + g0, g1 - g0, hdrs + groups, jobs + g0);
+    if (rc != LBM_OK) return rc;
+    ++groups;
+    g0 = g1;
   }
   return LBM_OK;
 }

@@ -24,6 +24,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_EUNS
 LBM_ALLOW_HIGH_MA, LBM_NO_GRAPH, LBM_FULL_ORDER, LBM_SPONGE_FIELD = 0x1, 0x2, 0x4, 0x8
 LBM_BGK, LBM_MRT = 0x10, 0x20
 LBM_MAX_LEVELS = 5
+LBM_NOALLOC_MAX_JOBS = 256
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f32s": LBM_F32S, "f16s": LBM_F16S,
            "m64": LBM_M64, "m32": LBM_M32}
@@ -34,7 +35,7 @@ EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memo
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
            "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_set_sponge", "lbm_get_populations", "lbm_set_populations",
-           "lbm_step_batch", "lbm_autotune", "lbm_halo_buffers", "lbm_halo_exchange",
+           "lbm_step_batch", "lbm_step_batch_noalloc", "lbm_autotune", "lbm_halo_buffers", "lbm_halo_exchange",
            "lbm_destroy", "lbm_lattice_table", "lbm_last_error"]
 
 
@@ -97,6 +98,7 @@ def lib():
         L.lbm_get_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
+        L.lbm_step_batch_noalloc.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_int]
         L.lbm_halo_buffers.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp),
                                        C.POINTER(C.c_size_t)]
@@ -205,6 +207,13 @@ def lbm_step_batch(ctxs, steps):
     arr = (C.c_void_p * n)(*[c.value for c in ctxs])
     st = (C.c_int64 * n)(*[int(s) for s in steps])
     return _check(lib().lbm_step_batch(arr, st, n))
+
+
+def lbm_step_batch_noalloc(ctxs, steps):
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.value for c in ctxs])
+    st = (C.c_int64 * n)(*[int(s) for s in steps])
+    return _check(lib().lbm_step_batch_noalloc(arr, st, n))
 
 
 def lbm_autotune(ctx, trials=3):

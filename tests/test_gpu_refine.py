@@ -174,6 +174,62 @@ def test_four_level_2d_parity_f64():
         assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
 
 
+FIVE_3D = dict(shape=(20, 20, 20), lo=(4, 4, 4), hi=(13, 13, 13),
+               nest=[((4, 4, 4), (14, 14, 14)), ((4, 4, 4), (16, 16, 16)),
+                     ((4, 4, 4), (20, 20, 20))])
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_five_level_3d_parity_f64(q):
+    """Level 0 and four nested boxes (the five levels of the jet setup of
+    Sec. IV), every level against the oracle's multi-level driver."""
+    case = dict(name="ml5-3d", q=q, tau=0.56, **FIVE_3D)
+    pops, og, sim = run_multilevel(case, 2)
+    assert len(og.grids) == 5
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+    assert sim.updates_per_step == sum(
+        int(((og.crole[l] == 0) & (og.ring[l] == 0)).sum()) << l for l in range(5))
+    assert sim.time == 2
+
+
+def test_five_level_2d_parity_f64():
+    case = dict(name="ml5-2d", q=9, shape=(40, 36, 1), lo=(8, 8, 0), hi=(30, 28, 0),
+                nest=[((8, 8, 0), (36, 32, 0)), ((10, 10, 0), (46, 40, 0)),
+                      ((12, 12, 0), (60, 48, 0))], tau=0.58)
+    pops, og, _ = run_multilevel(case, 3)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+
+
+def test_four_level_3d_parity_f64():
+    case = dict(name="ml4-3d", q=19, shape=(22, 20, 20), lo=(5, 4, 4), hi=(16, 14, 15),
+                nest=[((4, 4, 4), (17, 15, 17)), ((4, 5, 4), (22, 18, 22))], tau=0.6)
+    pops, og, _ = run_multilevel(case, 3)
+    assert len(og.grids) == 4
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+
+
+def test_five_level_open_boundaries_parity_f64():
+    """Five levels with an inlet disc drawing noise (counter blocks of five
+    levels), an outflow layer and free-slip / outflow faces on level 0."""
+    shape = (30, 22, 22)
+    mask = W.jet_inlet_mask(*shape, D=6)
+    box = ((4, 4, 4), (20, 18, 18))
+    case = dict(name="ml5-open", q=19, shape=shape, lo=(5, 4, 4), hi=(20, 17, 17),
+                nest=[box, box, box], tau=0.53, ma=0.2, seed=8, inlet_noise=0.02,
+                face_bc=(2, 2, 1, 1, 2, 2), sponge_width=(0, 5, 0, 0, 0, 0), chi_max=0.3,
+                masks=[mask, None, None, None, None])
+    pops, og, _ = run_multilevel(case, 3)
+    for l, g in enumerate(og.grids):
+        keep = og.crole[l] != 2
+        assert normwise(pops[l][:, keep], g.f[:, keep]) <= F64_TOL, l
+
+
 def test_three_level_open_boundaries_parity_f64():
     """Inlet disc with noise (counter blocks of three levels), sponge and
     free-slip/outflow faces on level 0, two nested boxes in the middle."""

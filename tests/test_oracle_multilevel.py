@@ -108,3 +108,78 @@ def test_shear_wave_across_two_nested_interfaces():
         assert err < 1e-3, (l, err)
     drift = abs(M.grids[0].moments()[0][normal0].sum() - m0) / m0
     assert drift < 1e-6
+
+
+def five_levels(q, **kw):
+    """Level 0 and four nested boxes, each at least 4 nodes inside its
+    parent (the jet setup of Sec. IV uses five levels)."""
+    if q == 9:
+        return O.MultiLevelGrid(9, 40, 36, 1, boxes=[((8, 8, 0), (30, 28, 0)),
+                                                     ((8, 8, 0), (36, 32, 0)),
+                                                     ((10, 10, 0), (46, 40, 0)),
+                                                     ((12, 12, 0), (60, 48, 0))], **kw)
+    return O.MultiLevelGrid(q, 20, 20, 20, boxes=[((4, 4, 4), (13, 13, 13)),
+                                                  ((4, 4, 4), (14, 14, 14)),
+                                                  ((4, 4, 4), (16, 16, 16)),
+                                                  ((4, 4, 4), (20, 20, 20))], **kw)
+
+
+@pytest.mark.parametrize("q", [9, 27])
+def test_five_level_uniform_flow_is_fixed_point_and_times(q):
+    u0 = np.array([0.04, -0.03, 0.02 if q != 9 else 0.0])
+    M = five_levels(q, tau=0.56)
+    assert M.nlevels == 5
+    taus = [g.g.tau for g in M.grids]
+    for a, b in zip(taus, taus[1:]):
+        assert b == pytest.approx((4 * a - 1) / 2, abs=1e-14)
+    for l, g in enumerate(M.grids):
+        M.init(l, np.full(g.N, 0.99), np.tile(u0[:, None], (1, g.N)))
+    f0 = [g.f.copy() for g in M.grids]
+    M.step(2)
+    assert [g.t for g in M.grids] == [2, 4, 8, 16, 32]
+    for g, f in zip(M.grids, f0):
+        assert np.abs(g.f - f).max() < 1e-14
+
+
+def shear_wave_five_levels(tau_bump=0.0):
+    """u_x = A sin(k y) through level 0 and four nested boxes (four
+    interfaces in a chain): maximum error of each level against the decay
+    solution A exp(-nu k^2 t) sin(k y), and the mass drift of level 0."""
+    n, tau, A, T = 64, 0.6, 1e-3, 120
+    M = O.MultiLevelGrid(9, n, n, 1, boxes=[((8, 16, 0), (40, 48, 0)),
+                                            ((16, 12, 0), (48, 52, 0)),
+                                            ((16, 16, 0), (48, 64, 0)),
+                                            ((16, 16, 0), (48, 80, 0))], tau=tau)
+    if tau_bump:
+        M.grids[-1].g.tau += tau_bump
+    k = 2 * math.pi / n
+    for l, g in enumerate(M.grids):
+        _, Y, _ = level_coords(M, l)
+        u = np.zeros((3, g.N))
+        u[0] = A * np.sin(k * Y)
+        p = np.zeros((6, g.N))
+        p[3] = -g.g.tau * CS2 * A * k * np.cos(k * Y) * 0.5 ** l
+        M.init(l, np.ones(g.N), u, p)
+    normal0 = M.crole[0] == O.NORMAL
+    m0 = M.grids[0].moments()[0][normal0].sum()
+    M.step(T)
+    amp = A * math.exp(-CS2 * (tau - 0.5) * k * k * T)
+    errs = []
+    for l, g in enumerate(M.grids):
+        _, Y, _ = level_coords(M, l)
+        keep = (M.crole[l] == O.NORMAL) & (M.ring[l] == 0)
+        errs.append(float(np.abs(g.moments()[1][0] - amp * np.sin(k * Y))[keep].max() / amp))
+    drift = abs(M.grids[0].moments()[0][normal0].sum() - m0) / m0
+    return errs, drift
+
+
+def test_shear_wave_across_four_nested_interfaces():
+    """Every level of a five-level chain within 2e-4 of the decay solution
+    (measured 3.1e-5 at most); the viscosity cs^2 (tau_l - 1/2) dx_l^2 / dt_l
+    is the same on every level only with tau_(l+1) = (4 tau_l - 1)/2, and an
+    innermost tau off by 0.05 (2.1 -> 2.15) fails the bar (6.4e-4)."""
+    errs, drift = shear_wave_five_levels()
+    assert max(errs) < 2e-4, errs
+    assert drift < 1e-6
+    bad, _ = shear_wave_five_levels(tau_bump=0.05)
+    assert bad[-1] > 2e-4, bad

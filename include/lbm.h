@@ -312,9 +312,32 @@ int lbm_totals(lbm_ctx* ctx, int level, double* out);
 /* Canonical FP64 copy of the stored populations of `level`, [q][N] in the
  * documented direction order, unshifted (device pointers).  Used for
  * checkpoint/resume and parity checks.  set also resets nothing else:
- * the step counter is kept. */
+ * the step counter is kept.  On a refined context every level is stored
+ * this way; a checkpoint also holds each interface (lbm_get_interface) and
+ * the time (lbm_time). */
 int lbm_get_populations(lbm_ctx* ctx, int level, double* out);
 int lbm_set_populations(lbm_ctx* ctx, int level, const double* in);
+
+/* Set the coarse time index of an initialised context (resume from a
+ * checkpoint; call after every lbm_init of the context, which resets it):
+ * level l's own time index becomes t * 2^l, which the inlet noise counter
+ * of later steps follows.  t >= 0. */
+int lbm_set_time(lbm_ctx* ctx, int64_t t);
+
+/* Checkpoint of the refinement interface between level `level` and level
+ * `level` + 1 (Sec. II.B): the parent's recorded pre-collision moments of
+ * the current coarse time, which the next step's RING fill at t + 1/2
+ * blends with the new ones (eq. convective, linear in time), and the other
+ * record buffer.  Opaque bytes in the record's storage type (FP64 for
+ * LBM_F64, FP32 otherwise), lbm_interface_bytes long (0 and an error if
+ * there is no such interface).  get copies them to `out`, set restores them
+ * from `in` (device pointers, asynchronous on the context's stream) on a
+ * context of the same configuration.  With the populations of every level
+ * and the time, a run of 2n steps equals n steps, save, restore into a
+ * fresh context, n steps, bitwise. */
+size_t lbm_interface_bytes(const lbm_ctx* ctx, int level);
+int lbm_get_interface(lbm_ctx* ctx, int level, void* out);
+int lbm_set_interface(lbm_ctx* ctx, int level, const void* in);
 
 /* Serving: advance ctxs[k] by steps[k] coarse steps, k < n, sharing
  * launches between contexts: the contexts are grouped by lattice, storage,

@@ -357,6 +357,32 @@ static int advance(lbm_ctx* ctx, int l, bool record_band, hipStream_t st) {
   return LBM_OK;
 }
 
+// Interface state between coarse steps: the two parent-side records
+// (M_l(t) first, then the other one), each rec_n nodes x 10 components of
+// the record type.  The band record is not state: the child's second sweep
+// rewrites every entry the IMPORT filter reads before the filter runs.
+static size_t interface_record_bytes(const lbm_ctx* ctx, const Refinement* R) {
+  return (size_t)R->rec_n * 10 * (ctx->cfg.storage == LBM_F64 ? 8 : 4);
+}
+
+size_t refined_interface_bytes(const lbm_ctx* ctx, int l) {
+  return 2 * interface_record_bytes(ctx, ctx->ref[l]);
+}
+
+int refined_copy_interface(lbm_ctx* ctx, int l, void* out, const void* in) {
+  Refinement* R = ctx->ref[l];
+  const size_t b = interface_record_bytes(ctx, R);
+  for (int k = 0; k < 2; ++k) {
+    void* rec = R->rec[R->prev ^ k];
+    hipError_t e = out ? hipMemcpyAsync((char*)out + k * b, rec, b, hipMemcpyDeviceToDevice,
+                                        ctx->stream)
+                       : hipMemcpyAsync(rec, (const char*)in + k * b, b,
+                                        hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_error(e, "interface record copy");
+  }
+  return LBM_OK;
+}
+
 int refined_record_parity(const lbm_ctx* ctx, int l) { return ctx->ref[l]->prev; }
 
 void set_refined_record_parity(lbm_ctx* ctx, int l, int parity) { ctx->ref[l]->prev = parity; }

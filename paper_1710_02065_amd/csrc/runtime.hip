@@ -3,6 +3,8 @@
 // sequences), observables and population import/export.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -750,6 +752,16 @@ int lbm_sync(lbm_ctx* ctx) {
 
 int64_t lbm_time(const lbm_ctx* ctx) { return ctx ? ctx->t : -1; }
 
+int lbm_set_time(lbm_ctx* ctx, int64_t t) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (t < 0 || t > (INT64_MAX >> kMaxLevels))
+    return set_error(LBM_EINVAL, "time index %lld out of range", (long long)t);
+  ctx->t = t;
+  for (int l = 0; l < ctx->nlevels; ++l) ctx->lv[l].t = t << l;
+  return LBM_OK;
+}
+
 int64_t lbm_updates_per_step(const lbm_ctx* ctx) {
   if (!ctx) return set_error(LBM_EINVAL, "ctx is NULL");
   return ctx->nlevels > 1 ? refined_updates_per_step(ctx) : ctx->lv[0].N;
@@ -954,10 +966,6 @@ int lbm_get_populations(lbm_ctx* ctx, int level, double* out) {
 int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
   int rc = check_ready(ctx);
   if (rc != LBM_OK) return rc;
-  if (ctx->nlevels > 1)
-    return set_error(LBM_EUNSUPPORTED,
-                     "set_populations on a refined context: the interface moments of the "
-                     "previous coarse step cannot be rebuilt from populations");
   if (level < 0 || level >= ctx->nlevels || !in)
     return set_error(LBM_EINVAL, "level %d / input", level);
   rc = ensure_device(ctx);
@@ -978,6 +986,35 @@ int lbm_set_populations(lbm_ctx* ctx, int level, const double* in) {
   if (e != hipSuccess) return hip_error(e, "set_populations launch");
   if (ctx->nlevels > 1) return refined_after_set(ctx, level);
   return pack_halos(ctx, false);
+}
+
+size_t lbm_interface_bytes(const lbm_ctx* ctx, int level) {
+  if (!ctx || level < 0 || level + 1 >= ctx->nlevels) {
+    (void)set_error(LBM_EINVAL, "no refinement interface below level %d", level);
+    return 0;
+  }
+  return refined_interface_bytes(ctx, level);
+}
+
+static int interface_io(lbm_ctx* ctx, int level, void* out, const void* in) {
+  int rc = check_ready(ctx);
+  if (rc != LBM_OK) return rc;
+  if (level < 0 || level + 1 >= ctx->nlevels)
+    return set_error(LBM_EINVAL, "no refinement interface below level %d", level);
+  if (!out && !in) return set_error(LBM_EINVAL, "interface buffer is NULL");
+  rc = ensure_device(ctx);
+  if (rc != LBM_OK) return rc;
+  return refined_copy_interface(ctx, level, out, in);
+}
+
+int lbm_get_interface(lbm_ctx* ctx, int level, void* out) {
+  if (!out) return set_error(LBM_EINVAL, "interface output is NULL");
+  return interface_io(ctx, level, out, nullptr);
+}
+
+int lbm_set_interface(lbm_ctx* ctx, int level, const void* in) {
+  if (!in) return set_error(LBM_EINVAL, "interface input is NULL");
+  return interface_io(ctx, level, nullptr, in);
 }
 
 int lbm_halo_buffers(lbm_ctx* ctx, int side, void** send, void** recv, size_t* bytes) {

@@ -127,6 +127,10 @@ int refined_after_init(lbm_ctx* ctx);
 int64_t refined_updates_per_step(const lbm_ctx* ctx);
 int refined_after_set(lbm_ctx* ctx, int level);
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st);
+// checkpoint of interface l: size and device-to-device copy of its records
+// (out != nullptr: export; else import from in)
+size_t refined_interface_bytes(const lbm_ctx* ctx, int l);
+int refined_copy_interface(lbm_ctx* ctx, int l, void* out, const void* in);
 // which of the two parent-side records of interface l holds M_l(t)
 int refined_record_parity(const lbm_ctx* ctx, int l);
 void set_refined_record_parity(lbm_ctx* ctx, int l, int parity);

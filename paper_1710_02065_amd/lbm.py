@@ -34,7 +34,9 @@ STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_F16S: 2, LBM_M64: 8, L
 EXPORTS = ["lbm_config_init", "lbm_required_bytes", "lbm_create", "lbm_bind_memory",
            "lbm_init", "lbm_step", "lbm_sync", "lbm_time", "lbm_updates_per_step",
            "lbm_level_shape",
-           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_set_sponge", "lbm_get_populations", "lbm_set_populations",
+           "lbm_moments", "lbm_probe", "lbm_accumulate", "lbm_force", "lbm_totals", "lbm_set_sponge",
+           "lbm_get_populations", "lbm_set_populations", "lbm_set_time", "lbm_interface_bytes",
+           "lbm_get_interface", "lbm_set_interface",
            "lbm_step_batch", "lbm_step_batch_noalloc", "lbm_autotune", "lbm_halo_buffers", "lbm_halo_exchange",
            "lbm_destroy", "lbm_lattice_table", "lbm_last_error"]
 
@@ -97,6 +99,11 @@ def lib():
         L.lbm_accumulate.argtypes = [vp, C.c_int, dp, dp]
         L.lbm_get_populations.argtypes = [vp, C.c_int, dp]
         L.lbm_set_populations.argtypes = [vp, C.c_int, dp]
+        L.lbm_set_time.argtypes = [vp, i64]
+        L.lbm_interface_bytes.argtypes = [vp, C.c_int]
+        L.lbm_interface_bytes.restype = C.c_size_t
+        L.lbm_get_interface.argtypes = [vp, C.c_int, vp]
+        L.lbm_set_interface.argtypes = [vp, C.c_int, vp]
         L.lbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
         L.lbm_step_batch_noalloc.argtypes = [C.POINTER(vp), C.POINTER(i64), C.c_int]
         L.lbm_autotune.argtypes = [vp, C.c_int]
@@ -200,6 +207,25 @@ def lbm_get_populations(ctx, level, out):
 
 def lbm_set_populations(ctx, level, inp):
     return _check(lib().lbm_set_populations(ctx, level, _ptr(inp)))
+
+
+def lbm_set_time(ctx, t):
+    return _check(lib().lbm_set_time(ctx, int(t)))
+
+
+def lbm_interface_bytes(ctx, level):
+    n = int(lib().lbm_interface_bytes(ctx, level))
+    if n == 0:
+        raise LbmError(LBM_EINVAL, lib().lbm_last_error().decode())
+    return n
+
+
+def lbm_get_interface(ctx, level, out):
+    return _check(lib().lbm_get_interface(ctx, level, _ptr(out)))
+
+
+def lbm_set_interface(ctx, level, inp):
+    return _check(lib().lbm_set_interface(ctx, level, _ptr(inp)))
 
 
 def lbm_step_batch(ctxs, steps):
@@ -414,6 +440,35 @@ class Simulation:
         f = self._dev(f, self.torch.float64)
         self._keep_f = f
         lbm_set_populations(self.ctx, level, f)
+
+    def checkpoint(self):
+        """Device copies of everything a resume needs: the time, the
+        populations of every level and the records of every refinement
+        interface."""
+        t = self.torch
+        nlev = self.levels
+        pops = [self.populations(l) for l in range(nlev)]
+        recs = []
+        for l in range(nlev - 1):
+            buf = t.empty(lbm_interface_bytes(self.ctx, l), dtype=t.uint8, device=self.device)
+            lbm_get_interface(self.ctx, l, buf)
+            recs.append(buf)
+        return dict(time=self.time, pops=pops, interfaces=recs)
+
+    def restore(self, ck):
+        """Resume from `checkpoint()` output (call after init of every level)."""
+        for l, f in enumerate(ck["pops"]):
+            self.set_populations(f, l)
+        self._keep_ck = ck
+        for l, buf in enumerate(ck["interfaces"]):
+            lbm_set_interface(self.ctx, l, buf)
+        lbm_set_time(self.ctx, ck["time"])
+        return self
+
+    @property
+    def levels(self):
+        refined = any(self.cfg.refine_lo[:]) or any(self.cfg.refine_hi[:])
+        return 1 + (1 + self.cfg.nest_count if refined else 0)
 
     def probe(self, cells, level=0):
         t = self.torch

@@ -111,17 +111,68 @@ def test_refined_shear_wave_f32_tracks_oracle():
     assert np.abs(ufg.cpu().numpy()[0] - ufo[0]).max() < 1e-6
 
 
-def test_refined_set_populations_unsupported():
-    from paper_1710_02065_amd import lbm
+def test_refined_layout_and_updates_per_step():
     case = dict(name="ref-set", q=9, shape=(32, 32, 1), lo=(8, 8, 0), hi=(20, 20, 0))
     sim = refined_sim(case, "f32")
     sim.init(level=0)
     sim.init(level=1)
-    f = sim.populations(0)
-    with pytest.raises(lbm.LbmError) as e:
-        sim.set_populations(f, 0)
-    assert e.value.code == lbm.LBM_EUNSUPPORTED
+    assert sim.levels == 2
     assert sim.updates_per_step == (32 * 32 - 11 * 11) + 2 * (25 * 25 - 4 * 24)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("noise", [True, False])
+def test_refined_checkpoint_resume_bitwise(storage, noise):
+    """Three levels with an inlet drawing noise (eager stepping) or without
+    (graph replays of two coarse steps): 2n coarse steps equal n steps,
+    checkpoint (time, populations of every level, interface records),
+    restore into a fresh context initialised with other fields, n steps,
+    bitwise on every level."""
+    from tests.pair import multilevel_sim
+    shape = (34, 26, 26)
+    mask = W.jet_inlet_mask(*shape, D=6)
+    case = dict(name="ml-ckpt", q=19, shape=shape, lo=(7, 6, 6), hi=(21, 19, 19),
+                nest=[((6, 6, 6), (20, 20, 20))], tau=0.52, ma=0.2, seed=3,
+                inlet_noise=0.02 if noise else 0.0, face_bc=(2, 2, 1, 1, 2, 2),
+                sponge_width=(0, 8, 0, 0, 0, 4), chi_max=0.3, masks=[mask, None, None])
+    n = 5
+    sims = []
+    for k in range(3):
+        log("refined checkpoint storage=%s noise=%s sim %d" % (storage, noise, k))
+        s = multilevel_sim(case, storage)
+        for l in range(3):
+            f = W.random_state(s.shape(l), seed=(40 if k < 2 else 90) + l, d=3, u_amp=0.03,
+                               rho_amp=0.01, pi_amp=5e-4)
+            s.init(*f, mask=case["masks"][l], level=l)
+        sims.append(s)
+    a, b, c = sims
+    a.step(2 * n)
+    b.step(n)
+    ck = b.checkpoint()
+    assert ck["time"] == n and len(ck["pops"]) == 3 and len(ck["interfaces"]) == 2
+    c.restore(ck)
+    assert c.time == n
+    c.step(n)
+    for l in range(3):
+        np.testing.assert_array_equal(c.populations(l).cpu().numpy(),
+                                      a.populations(l).cpu().numpy())
+    assert c.time == a.time == 2 * n
+    c.sync()
+
+
+def test_interface_checkpoint_arguments():
+    from paper_1710_02065_amd import lbm
+    case = dict(name="ref-args", q=9, shape=(32, 32, 1), lo=(8, 8, 0), hi=(20, 20, 0))
+    sim = refined_sim(case, "f32")
+    sim.init(level=0)
+    sim.init(level=1)
+    nb = lbm.lbm_interface_bytes(sim.ctx, 0)
+    assert nb == 2 * (13 + 2) * (13 + 2) * 10 * 4
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_interface_bytes(sim.ctx, 1)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_time(sim.ctx, -1)
+    assert e.value.code == lbm.LBM_EINVAL
 
 
 # ------------------------------------------------------------------------

@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# workgroup size of the timed headline sweep (D3Q19 FP32), fixed so that the
+# committed kernel trace and counters describe the launch this run times
+HEADLINE_BLOCK = 128
 METRIC = "MLUPS & % HBM roofline (D3Q19 256³); p50/p99 latency, batched serving"
 # sources each profiled kernel is compiled from
 SOURCES = {"k_sweep": ["kernels.hip", "kernels.hpp", "lattice.hpp"],
@@ -64,10 +67,12 @@ def measured_traffic(name):
     return int(d["bytes_per_launch"])
 
 
-def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0, lattice=19, flags=0):
+def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0, lattice=19, flags=0,
+            windows=1):
     """Initialise, warm up, pick the workgroup size with the library's
-    autotuner (unless one is given), then time `steps` steps with HIP events
-    on the launch stream."""
+    autotuner (unless one is given), then time `windows` windows of `steps`
+    steps each with HIP events on the launch stream; returns the simulation,
+    the median window in ms and every window."""
     rho, u = fields
     sim = lbm.Simulation(lattice=lattice, shape=(n, n, n), tau=0.52, storage=storage,
                          block=block, flags=flags)
@@ -78,16 +83,18 @@ def run_gpu(lbm, torch, storage, n, steps, warmup, fields, block=0, lattice=19, 
     sim.step(2)
     sim.sync()
     stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    sim.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
+    times = []
+    for _ in range(windows):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        sim.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        times.append(t0.elapsed_time(t1))
     sim.sync()
-    ms = t0.elapsed_time(t1)
-    return sim, ms
+    return sim, float(np.median(times)), times
 
 
 def copy_bandwidth(torch, nbytes=2 ** 31, reps=10):
@@ -120,24 +127,40 @@ def pressure_error(sim, ref_rho, rho0=1.0):
     return float(((p - pref).norm() / pref.norm()).item()), r, u
 
 
-def cpu_baseline(n, seconds):
-    """The FP64 oracle on the host cores over the same 256^3 workload:
-    initialisation, then whole-grid steps until `seconds` have elapsed."""
-    import numpy as np
+def anchor_states(lbm, torch, n, fields, steps, storages=("f64", "f32", "f16s", "m32")):
+    """The headline workload stepped `steps` times from the same fields in
+    each storage; host copies of rho and u (and of the FP64 build's
+    populations) for the comparison with the oracle in the CPU leg."""
+    out = {}
+    for st in storages:
+        sim = lbm.Simulation(lattice=19, shape=(n, n, n), tau=0.52, storage=st)
+        sim.init(*fields)
+        sim.step(steps)
+        r, u = sim.moments()
+        out[st] = dict(rho=r.cpu().numpy(), u=u.cpu().numpy())
+        if st == "f64":
+            out[st]["pops"] = sim.populations().cpu().numpy()
+        sim.sync()
+        del sim, r, u
+        torch.cuda.empty_cache()
+    return out
 
+
+def cpu_baseline(n, steps, anchors=None):
+    """The FP64 oracle on the host cores over the same 256^3 workload:
+    initialisation, then `steps` timed whole-grid steps.  Its final state is
+    also the direct anchor of the GPU storages stepped as many times from the
+    same fields (`anchors`, from anchor_states): relative L2 error of the
+    acoustic pressure p' = cs^2 (rho - rho0) and of u, and for the FP64 build
+    the normwise population error."""
     import oracle as O
     from paper_1710_02065_amd import workloads as W
     U = 0.1 / math.sqrt(3)
     rho, u = W.taylor_green_3d(n, U, pulse_amp=1e-3, pulse_sigma=8.0)
     g = O.Grid(19, n, n, n, tau=0.52).init(rho, u)
     del rho, u
-    steps = 0
     t0 = time.perf_counter()
-    while True:
-        g.step(1)
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
+    g.step(steps)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     try:
@@ -145,9 +168,25 @@ def cpu_baseline(n, seconds):
     except AttributeError:
         avail = os.cpu_count()
     cores = min(threads, avail) if threads > 0 else avail
-    return dict(value=round(g.N * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
-                sample="FP64 oracle, D3Q19 %d^3 Taylor-Green + pulse, %d whole-grid steps "
-                       "(%.1f s) after initialisation" % (n, steps, dt))
+    res = dict(value=round(g.N * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+               sample="FP64 oracle, D3Q19 %d^3 Taylor-Green + pulse, %d whole-grid steps "
+                      "(%.1f s) after initialisation" % (n, steps, dt))
+    if anchors:
+        r_o, u_o = g.moments()
+        p_o = (r_o - 1.0) / 3.0
+        rows = {}
+        for st, a in anchors.items():
+            row = dict(p_rel_l2=float(np.linalg.norm((a["rho"] - 1.0) / 3.0 - p_o)
+                                      / np.linalg.norm(p_o)),
+                       u_rel_l2=float(np.linalg.norm(a["u"] - u_o) / np.linalg.norm(u_o)))
+            if "pops" in a:
+                row["populations_normwise"] = float(np.abs(a["pops"] - g.f).max()
+                                                    / np.abs(g.f).max())
+            rows[st] = row
+        res["anchor_vs_gpu"] = dict(
+            steps=steps, errors=rows,
+            note="GPU storages against this oracle run, same fields and steps, whole grid")
+    return res
 
 
 def precision_study(lbm, torch, n, fields, horizons):
@@ -405,7 +444,76 @@ def other_configs(lbm, torch, steps, shedding_steps,
                         "similarity velocity as reference" if field else ""))
             del sim
             torch.cuda.empty_cache()
+        # FP32 against the FP64 build (which the parity tests match to the
+        # oracle within 1e-12 on reduced refined jets) after a short horizon,
+        # per level, over the swept cells
+        horizon = 100
+        mom = {}
+        for st in ("f64", "f32"):
+            sim = lbm.Simulation(lattice=27, shape=shape, tau=tau, storage=st, ma=0.3,
+                                 face_bc=(2, 2, 2, 2, 2, 2), sponge_width=widths,
+                                 chi_max=0.2, rho_ref=1.0, seed=4, inlet_noise=0.02,
+                                 refine_lo=lo, refine_hi=hi)
+            for lev in (0, 1):
+                ls = sim.shape(lev)
+                sim.init(None, torch.zeros(3, ls[0] * ls[1] * ls[2], dtype=torch.float64,
+                                           device="cuda"), None,
+                         W.jet_inlet_mask(*shape, D=20) if lev == 0 else None, level=lev)
+            sim.step(horizon)
+            mom[st] = [sim.moments(lev) for lev in (0, 1)]
+            sim.sync()
+            del sim
+            torch.cuda.empty_cache()
+        err = {}
+        for lev in (0, 1):
+            (r64, u64), (r32, u32) = mom["f64"][lev], mom["f32"][lev]
+            live = r64 != 0  # SOLID and COVERED cells report 0
+            p64 = (r64 - 1.0)[live]
+            err["level%d" % lev] = dict(
+                p_rel_l2=float((r32 - r64)[live].norm() / p64.norm()),
+                u_rel_l2=float((u32 - u64)[:, live].norm() / u64[:, live].norm()))
+        res["d3q27_jet_384x256x256_refined_f32_vs_f64"] = dict(
+            coarse_steps=horizon, errors=err,
+            note="FP32 storage against the FP64 build of the same run (same inlet noise); "
+                 "p' = cs^2 (rho - rho0)")
+        del mom
+        torch.cuda.empty_cache()
     return res
+
+
+def serving_errors(be, lbm, torch, side=256, steps=2000):
+    """Storage error of the served job kinds: the smallest jobs of the mix
+    (side x side, the shortest length) in FP32 and FP16-shifted storage
+    against the FP64 build of the same job (same fields, noise and step
+    count; the parity tests match served FP64 jobs to the oracle within
+    1e-12): relative L2 error of p' = cs^2 (rho - rho0) and of u."""
+    out = {}
+    for kind in ("cylinder", "pulse"):
+        res = {}
+        for st in ("f64", "f32", "f16s"):
+            job = dict(id=0, kind=kind, nx=side, ny=side, ma=0.2, steps=steps, seed=7,
+                       storage=st, arrival=0.0)
+            h = be.start(job)
+            lbm.lbm_step(h["ctx"], steps)
+            rho = torch.empty(side * side, dtype=torch.float64, device="cuda")
+            u = torch.empty(3, side * side, dtype=torch.float64, device="cuda")
+            lbm.lbm_moments(h["ctx"], 0, rho, u)
+            be.finish(h)
+            res[st] = (rho, u)
+        r64, u64 = res["f64"]
+        live = r64 != 0
+        p64 = (r64 - 1.0)[live]
+        out[kind] = {st: dict(p_rel_l2=float((res[st][0] - r64)[live].norm() / p64.norm()),
+                              u_rel_l2=float((res[st][1] - u64)[:, live].norm()
+                                             / u64[:, live].norm()),
+                              rho_max_abs=float((res[st][0] - r64)[live].abs().max()))
+                     for st in ("f32", "f16s")}
+    out["job"] = "%d x %d, Ma 0.2, %d steps" % (side, side, steps)
+    out["note"] = ("p' relative L2 is over the whole p' field; in the periodic pulse job the "
+                   "1e-3 pulse has spread over the box after 2000 steps, so p' is small and its "
+                   "relative error large; rho_max_abs is the largest density error, to be read "
+                   "against the initial pulse amplitude 1e-3")
+    return out
 
 
 def serving_bench(n_jobs, step_scale, loads, budget_gib, quantum):
@@ -432,7 +540,9 @@ def serving_bench(n_jobs, step_scale, loads, budget_gib, quantum):
             p99_latency_s=round(st["p99_latency_s"], 4), p50_queue_s=round(st["p50_queue_s"], 4),
             p99_queue_s=round(st["p99_queue_s"], 4), mlups=round(st["mlups"], 1),
             peak_resident_gib=round(st["peak_bytes"] / 2 ** 30, 3))
+    errors = serving_errors(be, be.lbm, be.torch)
     return dict(
+        storage_error_vs_f64=errors,
         workload="D2Q9 job mix: half cylinder channels, half acoustic pulses, sides U{256..2048}, "
                  "Ma U[0.05, 0.3], steps U{2000..20000} x %g, half FP32 / half FP16-shifted "
                  "storage, Poisson arrivals (seed 5)" % step_scale,
@@ -448,11 +558,16 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--block", type=int, default=-1,
+                    help="workgroup size of the headline sweep (-1: the fixed HEADLINE_BLOCK "
+                         "for FP32, the autotuner for M32; 0: the autotuner)")
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of --steps steps each; the median is reported")
     ap.add_argument("--storage", default="f32", choices=["f32", "m32"],
                     help="storage of the timed headline run: FP32 populations, or the "
                          "FP32 moment storage (10 values per cell)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="whole-grid oracle steps of the CPU leg (about 20 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -464,11 +579,11 @@ def main():
     ap.add_argument("--shedding-steps", type=int, default=160000,
                     help="cylinder channel steps for C_L / St (0: skip)")
     ap.add_argument("--precision-horizons", type=lambda s: [int(x) for x in s.split(",")],
-                    default=[500, 1000, 2000, 5000])
-    ap.add_argument("--serve-jobs", type=int, default=256)
-    ap.add_argument("--serve-step-scale", type=float, default=0.1)
+                    default=[50, 100, 200, 500, 1000, 2000, 5000])
+    ap.add_argument("--serve-jobs", type=int, default=160)
+    ap.add_argument("--serve-step-scale", type=float, default=1.0)
     ap.add_argument("--serve-loads", type=lambda s: [float(x) for x in s.split(",")],
-                    default=[0.5, 0.8, 1.0])
+                    default=[0.5, 0.8])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-quantum", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -509,7 +624,9 @@ def main():
     hs = args.storage
     moment = hs == "m32"
     log("timing %s: %d warmup + %d steps" % (hs, args.warmup, args.steps))
-    sim32, ms32 = run_gpu(lbm, torch, hs, n, args.steps, args.warmup, fields, args.block)
+    block = args.block if args.block >= 0 else (0 if moment else HEADLINE_BLOCK)
+    sim32, ms32, windows = run_gpu(lbm, torch, hs, n, args.steps, args.warmup, fields, block,
+                                   windows=args.windows)
     mlups32 = N * args.steps / (ms32 * 1e3)
     bytes_lup = 2 * (10 if moment else 19) * 4
     per_launch_s = ms32 / 1e3 / args.steps
@@ -525,7 +642,8 @@ def main():
     if not args.no_variants:
         for st in [v for v in ("f32", "f16s", "f32s", "f64", "m32", "m64") if v != hs]:
             log("timing %s" % st)
-            sv, msv = run_gpu(lbm, torch, st, n, args.steps, args.warmup, fields, args.block)
+            sv, msv, _ = run_gpu(lbm, torch, st, n, args.steps, args.warmup, fields,
+                                 HEADLINE_BLOCK if st == "f32" else 0)
             # the moment storages move 10 values per cell each way, not 19
             vals = 10 if st.startswith("m") else 19
             b = 2 * vals * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
@@ -543,8 +661,8 @@ def main():
         for st in ("f32", "f16s", "m32"):
             for name, fl in (("third", 0), ("full", lbm.LBM_FULL_ORDER)):
                 log("timing d3q27 %s %s" % (st, name))
-                sv, msv = run_gpu(lbm, torch, st, n, max(args.steps // 4, 50), args.warmup // 4,
-                                  fields, args.block, lattice=27, flags=fl)
+                sv, msv, _ = run_gpu(lbm, torch, st, n, max(args.steps // 4, 50),
+                                     args.warmup // 4, fields, 0, lattice=27, flags=fl)
                 b = 2 * (10 if st.startswith("m") else 27) * lbm.STORAGE_BYTES[lbm.STORAGE[st]]
                 ns = max(args.steps // 4, 50)
                 order["d3q27_%s_%s" % (st, name)] = dict(
@@ -564,6 +682,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms32 / args.steps, 5),
+        "timing": "median of %d windows of %d steps (HIP events on the launch stream); "
+                  "every window in ms: %s" % (len(windows), args.steps,
+                                             ", ".join("%.4f" % w for w in windows)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -587,6 +708,14 @@ def main():
         out["variants"] = variants
     if precision:
         out["precision_vs_f64_build"] = precision
+        if "f16s" in variants:
+            meets = [int(T) for T, row in precision.items() if row["f16s"]["p_rel_l2"] <= 1e-3]
+            out["f16s_speedup_at_1e-3"] = {
+                "speedup_vs_f32": variants["f16s"]["speedup_vs_headline"],
+                "horizons_within_1e-3": meets,
+                "note": "FP16-shifted storage over FP32 on the same GPU; the horizons (steps) "
+                     "at which its acoustic-pressure error against the FP64 build is at most "
+                     "1e-3 relative (none: it meets the bar at no horizon measured)"}
     out["config"]["workgroup"] = wg32
     if not args.no_sharding and n % 8 == 0:
         log("slab decomposition rehearsal (8 z-slabs)")
@@ -602,8 +731,14 @@ def main():
                                        args.serve_budget_gib, args.serve_quantum)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ~%.0f s" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+        anchors = None
+        if not args.no_variants:
+            log("anchor runs: %d steps in each storage" % args.cpu_steps)
+            anchors = anchor_states(lbm, torch, n, fields, args.cpu_steps)
+        del fields
+        torch.cuda.empty_cache()
+        log("cpu baseline (oracle): %d steps" % args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, anchors)
     print(json.dumps(out), flush=True)
 
 

@@ -219,6 +219,78 @@ __device__ __forceinline__ void record_moments(const SweepArgs<S>& a,
   }
 }
 
+// Interpolation points and weights of a child node coordinate k along one
+// axis (the child box starts at parent coordinate lo): a coincident node
+// copies its parent node; a midpoint takes the local cubic (-1, 9, 9, -1)/16.
+__device__ __forceinline__ int axis_points(int32_t lo, uint32_t k, int32_t pts[4],
+                                           float wts[4]) {
+  if ((k & 1u) == 0) {
+    pts[0] = lo + (int32_t)(k >> 1);
+    wts[0] = 1.0f;
+    return 1;
+  }
+  const int32_t j = lo + (int32_t)(k >> 1);
+  pts[0] = j - 1;
+  pts[1] = j;
+  pts[2] = j + 1;
+  pts[3] = j + 2;
+  wts[0] = -1.0f / 16.0f;
+  wts[1] = 9.0f / 16.0f;
+  wts[2] = 9.0f / 16.0f;
+  wts[3] = -1.0f / 16.0f;
+  return 4;
+}
+
+// RING node state (eq. couplingFC): interpolated rho~, u~, Pi~_neq (cubic
+// in space, linear in time: wa Ma + wb Mb of the parent's two recorded
+// time levels), Pi_neq rescaled by alpha_cf = tau_f / (2 tau_c), then
+// f = f^{eqH}(rho~, u~) + (1 - 1/tau_f) f^{neqH}(alpha_cf Pi~_neq, u~),
+// encoded for storage.  k: the node's coordinates on the child level.
+template <class L, class S>
+__device__ __forceinline__ void ring_node(const typename S::R* Ma, const typename S::R* Mb,
+                                          typename S::R wa, typename S::R wb,
+                                          typename S::R alpha, typename S::R omega1,
+                                          typename S::R rho0, const int32_t lo[3],
+                                          const int32_t rec_off[3], const uint32_t rec_dim[3],
+                                          const uint32_t k[3], typename S::T vals[L::Q]) {
+  using R = typename S::R;
+  int32_t pts[3][4];
+  float wts[3][4];
+  int np[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax < L::D) {
+      np[ax] = axis_points(lo[ax], k[ax], pts[ax], wts[ax]);
+    } else {
+      np[ax] = 1;
+      pts[ax][0] = rec_off[ax];
+      wts[ax][0] = 1.0f;
+    }
+  }
+  R m[10];
+  for (int q = 0; q < 10; ++q) m[q] = (R)0;
+  for (int i2 = 0; i2 < np[2]; ++i2)
+    for (int i1 = 0; i1 < np[1]; ++i1)
+      for (int i0 = 0; i0 < np[0]; ++i0) {
+        const uint64_t r =
+            ((uint64_t)(pts[2][i2] - rec_off[2]) * rec_dim[1] +
+             (uint64_t)(pts[1][i1] - rec_off[1])) * rec_dim[0] +
+            (uint64_t)(pts[0][i0] - rec_off[0]);
+        const R w = (R)wts[0][i0] * (R)wts[1][i1] * (R)wts[2][i2];
+        for (int q = 0; q < 10; ++q) {
+          const uint64_t o = r * 10 + (uint64_t)q;
+          m[q] += w * (wa * Ma[o] + wb * Mb[o]);
+        }
+      }
+  R u[3] = {m[1], m[2], L::D == 3 ? m[3] : (R)0};
+  R a2[6];
+  for (int q = 0; q < 6; ++q) a2[q] = alpha * m[4 + q];
+  if (L::D == 2) a2[2] = a2[4] = a2[5] = (R)0;
+  R out[L::Q];
+  rebuild_state<L, R>(m[0], rho0, u, a2, omega1, out);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) vals[i] = encode<S>(out[i], (R)L::w(i) * rho0);
+}
+
 // ------------------------------------------------------------------------
 // The sweep: pull-stream + (sponge) + regularized collision + store.
 // kGeneral = false: every face periodic (or a halo face of the last axis),
@@ -264,6 +336,20 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
     if (!plain) m = a.mask ? a.mask[c] : kFluid;
     pull_periodic<L, S>(a, c, x, y, z, raw);
     const uint8_t kind = m & kKindBits;
+    if (kind == kRing && a.ring_Ma) {
+      // a RING node of this (child) level: the coarse-to-fine fill for the
+      // state this sweep produces, written here so that its stores join the
+      // sweep's own instead of a separate scattered pass
+      const uint32_t k[3] = {x, y, z};
+      T vals[Q];
+      ring_node<L, S>(a.ring_Ma, a.ring_Mb, a.ring_wa, a.ring_wb, a.ring_alpha, a.omega1,
+                      a.rho0, a.ring_lo, a.ring_off, a.ring_dim, k, vals);
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        store_pop_nt(a.dst + (uint64_t)i * P, (uint32_t)(P * sizeof(T)), c, vals[i]);
+      });
+      return;
+    }
     if (kind == kSolid || kind >= kCovered) return;
     // one rebuild for every kind of cell keeps the kernel's code compact
     // (the comparators collide without it)
@@ -807,31 +893,8 @@ __global__ void k_record_fields(RecordFieldsArgs a) {
   }
 }
 
-// Interpolation points along one axis for fine index k (eq. couplingFC):
-// the coincident coarse node, or for a midpoint the local cubic
-// (-1, 9, 9, -1)/16 over the four nearest coarse nodes.
-__device__ __forceinline__ int axis_points(int32_t lo, uint32_t k, int32_t pts[4],
-                                           float wts[4]) {
-  if ((k & 1u) == 0) {
-    pts[0] = lo + (int32_t)(k >> 1);
-    wts[0] = 1.0f;
-    return 1;
-  }
-  const int32_t j = lo + (int32_t)(k >> 1);
-  pts[0] = j - 1;
-  pts[1] = j;
-  pts[2] = j + 1;
-  pts[3] = j + 2;
-  wts[0] = -1.0f / 16.0f;
-  wts[1] = 9.0f / 16.0f;
-  wts[2] = 9.0f / 16.0f;
-  wts[3] = -1.0f / 16.0f;
-  return 4;
-}
-
-// RING node state: interpolated rho~, u~, Pi~_neq (cubic in space, linear
-// in time), Pi_neq rescaled by alpha_cf = tau_f / (2 tau_c), then
-// f = f^{eqH}(rho~, u~) + (1 - 1/tau_f) f^{neqH}(alpha_cf Pi~_neq, u~).
+// RING nodes of a child level from a list (the fill after initialisation;
+// during stepping the child's sweep rebuilds them itself, see sweep_cell).
 template <class L, class S>
 __global__ void k_ring(RingArgs a) {
   using R = typename S::R;
@@ -840,46 +903,12 @@ __global__ void k_ring(RingArgs a) {
   if (n >= a.n) return;
   const uint32_t cf = a.list[n];
   const uint32_t k[3] = {cf % a.fnx, (cf / a.fnx) % a.fny, cf / (a.fnx * a.fny)};
-  int32_t pts[3][4];
-  float wts[3][4];
-  int np[3];
-  for (int ax = 0; ax < 3; ++ax) {
-    if (ax < L::D) {
-      np[ax] = axis_points(a.lo[ax], k[ax], pts[ax], wts[ax]);
-    } else {
-      np[ax] = 1;
-      pts[ax][0] = a.rec_off[ax];
-      wts[ax][0] = 1.0f;
-    }
-  }
-  const R* Ma = (const R*)a.Ma;
-  const R* Mb = (const R*)a.Mb;
-  const R wa = (R)a.wa, wb = (R)a.wb;
-  R m[10];
-  for (int q = 0; q < 10; ++q) m[q] = (R)0;
-  for (int i2 = 0; i2 < np[2]; ++i2)
-    for (int i1 = 0; i1 < np[1]; ++i1)
-      for (int i0 = 0; i0 < np[0]; ++i0) {
-        const uint64_t r =
-            ((uint64_t)(pts[2][i2] - a.rec_off[2]) * a.rec_dim[1] +
-             (uint64_t)(pts[1][i1] - a.rec_off[1])) * a.rec_dim[0] +
-            (uint64_t)(pts[0][i0] - a.rec_off[0]);
-        const R w = (R)wts[0][i0] * (R)wts[1][i1] * (R)wts[2][i2];
-        for (int q = 0; q < 10; ++q) {
-          const uint64_t o = r * 10 + (uint64_t)q;
-          m[q] += w * (wa * Ma[o] + wb * Mb[o]);
-        }
-      }
-  R u[3] = {m[1], m[2], L::D == 3 ? m[3] : (R)0};
-  R a2[6];
-  for (int q = 0; q < 6; ++q) a2[q] = (R)a.alpha * m[4 + q];
-  if (L::D == 2) a2[2] = a2[4] = a2[5] = (R)0;
-  R out[L::Q];
-  rebuild_state<L, R>(m[0], (R)a.rho0, u, a2, (R)a.omega1, out);
+  T vals[L::Q];
+  ring_node<L, S>((const R*)a.Ma, (const R*)a.Mb, (R)a.wa, (R)a.wb, (R)a.alpha, (R)a.omega1,
+                  (R)a.rho0, a.lo, a.rec_off, a.rec_dim, k, vals);
   T* dst = (T*)a.dst;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    dst[(uint64_t)i * a.pstride + cf] = encode<S>(out[i], (R)L::w(i) * (R)a.rho0);
+  for (int i = 0; i < L::Q; ++i) dst[(uint64_t)i * a.pstride + cf] = vals[i];
 }
 
 // IMPORT node state (eq. couplingCF): rho, u of the coincident child node
@@ -977,6 +1006,16 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
     a.box_hi[k] = h.box_hi[k];
   }
   a.rec_n = h.rec_n;
+  a.ring_Ma = (const R*)h.ring_Ma;
+  a.ring_Mb = (const R*)h.ring_Mb;
+  a.ring_wa = (R)h.ring_wa;
+  a.ring_wb = (R)h.ring_wb;
+  a.ring_alpha = (R)h.ring_alpha;
+  for (int k = 0; k < 3; ++k) {
+    a.ring_lo[k] = h.ring_lo[k];
+    a.ring_off[k] = h.ring_off[k];
+    a.ring_dim[k] = h.ring_dim[k];
+  }
   for (int k = 0; k < 2; ++k) {
     a.hrecv[k] = (const T*)h.hrecv[k];
     a.hsend[k] = (T*)h.hsend[k];

@@ -179,6 +179,16 @@ struct SweepArgs {
   // components per node, indexed by the node over all ncell nodes of this
   // level); nullptr disables it
   R* recf;
+  // refinement, child side: RING nodes rebuilt by this sweep from the
+  // parent's records ring_wa * ring_Ma + ring_wb * ring_Mb (record box
+  // [ring_off, ring_off + ring_dim) in parent coordinates, this level's box
+  // at ring_lo, stress scaled by ring_alpha); ring_Ma == nullptr: RING nodes
+  // are not written
+  const R* ring_Ma;
+  const R* ring_Mb;
+  R ring_wa, ring_wb, ring_alpha;
+  int32_t ring_lo[3], ring_off[3];
+  uint32_t ring_dim[3];
   // absorbing layer given per cell: chi, rho_ref, u_ref (5 x ncell), read
   // for cells flagged kFieldSponge; nullptr: none
   const R* sp;

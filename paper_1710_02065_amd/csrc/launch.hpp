@@ -42,6 +42,14 @@ struct SweepHost {
   int32_t box_lo[3], box_hi[3];
   // child-side record of the import band (nullptr: off)
   void* recf;
+  // RING nodes of this level rebuilt by the sweep from the parent's records
+  // ring_wa * Ma + ring_wb * Mb (ring_Ma nullptr: RING nodes left as they
+  // are); the parent-side record geometry and alpha_cf = tau / (2 tau_parent)
+  const void* ring_Ma;
+  const void* ring_Mb;
+  double ring_wa, ring_wb, ring_alpha;
+  int32_t ring_lo[3], ring_off[3];
+  uint32_t ring_dim[3];
   // absorbing layer given per cell (5 x N values of the compute type)
   const void* sp;
   // halo faces of the last axis, side 0 = low, 1 = high (nullptr: none;

@@ -12,10 +12,13 @@
 // One step of level l (level-l time t -> t+1), recursively:
 //   1. sweep level l; it records its pre-collision moments M_l(t+1) on the
 //      boundary planes of its child's box;
-//   2. if level l has a child: step the child; RING <- M_l(t + 1/2) =
-//      (M_l(t) + M_l(t+1)) / 2; step the child, whose sweep records its
-//      pre-collision moments in the import band; RING <- M_l(t+1);
-//      IMPORT <- filtered child moments.
+//   2. if level l has a child: step the child, whose sweep sets its RING
+//      to M_l(t + 1/2) = (M_l(t) + M_l(t+1)) / 2; step the child again, its
+//      sweep recording its pre-collision moments in the import band and
+//      setting the RING to M_l(t+1); IMPORT <- filtered child moments.
+//      (The RING nodes are read only by the child's next sweep, so writing
+//      them in the sweep that produces that state equals filling them after
+//      it.)
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -299,16 +302,40 @@ int refined_after_init(lbm_ctx* ctx) {
 
 int refined_after_set(lbm_ctx*, int) { return LBM_OK; }
 
+// The RING state a child sweep writes: wa * Ma + wb * Mb of its parent's
+// recorded moments.
+struct RingSource {
+  const void* Ma;
+  const void* Mb;
+  double wa, wb;
+};
+
 // One step of level l and, recursively, two of each finer level.
 // record_band: this is the second step of level l within its parent's
 // step, whose pre-collision moments the parent's IMPORT nodes filter.
-static int advance(lbm_ctx* ctx, int l, bool record_band, hipStream_t st) {
+// ring: the time blend of the parent's records the sweep of level l writes
+// into its RING nodes for the state it produces (nullptr on level 0).
+static int advance(lbm_ctx* ctx, int l, bool record_band, const RingSource* ring,
+                   hipStream_t st) {
   Level& L = ctx->lv[l];
   const bool has_child = l + 1 < ctx->nlevels;
   Refinement* R = has_child ? ctx->ref[l] : nullptr;
   const int next = R ? R->prev ^ 1 : 0;
-  // 1. sweep of level l
+  // 1. sweep of level l (its RING nodes rebuilt by the same sweep)
   SweepHost h = sweep_args(ctx, l, L.cur, (uint64_t)(L.t + 1));
+  if (ring) {
+    const Refinement* P = ctx->ref[l - 1];
+    h.ring_Ma = ring->Ma;
+    h.ring_Mb = ring->Mb;
+    h.ring_wa = ring->wa;
+    h.ring_wb = ring->wb;
+    h.ring_alpha = L.tau / (2.0 * ctx->lv[l - 1].tau);
+    for (int k = 0; k < 3; ++k) {
+      h.ring_lo[k] = P->lo[k];
+      h.ring_off[k] = P->rec_off[k];
+      h.ring_dim[k] = P->rec_dim[k];
+    }
+  }
   if (R) {
     h.rec = R->rec[next];
     for (int k = 0; k < 3; ++k) {
@@ -325,14 +352,13 @@ static int advance(lbm_ctx* ctx, int l, bool record_band, hipStream_t st) {
   L.cur ^= 1;
   L.t += 1;
   if (!R) return LBM_OK;
-  // 2. two child steps with the RING set at t + 1/2 and t + 1
-  int rc = advance(ctx, l + 1, false, st);
+  // 2. two child steps; their sweeps set the RING at t + 1/2 and t + 1
+  //    (the parent's record of M_l(t + 1) is complete: step 1 wrote it)
+  const RingSource half{R->rec[R->prev], R->rec[next], 0.5, 0.5};
+  const RingSource full{R->rec[next], R->rec[next], 1.0, 0.0};
+  int rc = advance(ctx, l + 1, false, &half, st);
   if (rc != LBM_OK) return rc;
-  rc = fill_ring(ctx, l, R->rec[R->prev], 0.5, R->rec[next], 0.5, st);
-  if (rc != LBM_OK) return rc;
-  rc = advance(ctx, l + 1, true, st);
-  if (rc != LBM_OK) return rc;
-  rc = fill_ring(ctx, l, R->rec[next], 1.0, R->rec[next], 0.0, st);
+  rc = advance(ctx, l + 1, true, &full, st);
   if (rc != LBM_OK) return rc;
   //    IMPORT from the child's pre-collision moments at the common time
   const Level& F = ctx->lv[l + 1];
@@ -388,7 +414,7 @@ int refined_record_parity(const lbm_ctx* ctx, int l) { return ctx->ref[l]->prev;
 void set_refined_record_parity(lbm_ctx* ctx, int l, int parity) { ctx->ref[l]->prev = parity; }
 
 int refined_coarse_step(lbm_ctx* ctx, hipStream_t st) {
-  int rc = advance(ctx, 0, false, st);
+  int rc = advance(ctx, 0, false, nullptr, st);
   if (rc != LBM_OK) return rc;
   ctx->t += 1;
   return LBM_OK;

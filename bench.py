@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # workgroup size of the timed headline sweep (D3Q19 FP32), fixed so that the
 # committed kernel trace and counters describe the launch this run times
-HEADLINE_BLOCK = 128
+HEADLINE_BLOCK = 256
 METRIC = "MLUPS & % HBM roofline (D3Q19 256³); p50/p99 latency, batched serving"
 # sources each profiled kernel is compiled from
 SOURCES = {"k_sweep": ["kernels.hip", "kernels.hpp", "lattice.hpp"],

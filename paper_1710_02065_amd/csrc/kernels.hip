@@ -427,11 +427,21 @@ template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
     __attribute__((amdgpu_waves_per_eu(SweepWaves<L, S, kGeneral>::value)))
     k_sweep(const SweepArgs<S> a) {
-  // Tile b goes to workgroup b: the hardware deals workgroups round-robin
-  // to the eight XCDs, so all XCDs stream through neighbouring tiles at the
-  // same time (measured faster here than giving each XCD a contiguous eighth
-  // of the grid: this sweep shares no data between tiles through L2).
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  // The hardware deals workgroups round-robin to the eight XCDs, so all
+  // XCDs stream through neighbouring tiles at the same time (measured faster
+  // than giving each XCD a contiguous eighth of the grid).  A pull reads
+  // the 128-byte lines at a tile's ends together with the neighbouring
+  // tile; with tiles shorter than 256 cells, runs of xcd_group consecutive
+  // tiles (256 cells) go to one XCD so that its L2 fetches those lines
+  // once: workgroup b of each block of 8 xcd_group workgroups takes tile
+  // (b mod 8) xcd_group + (b div 8) of that block (the tail keeps b).
+  uint32_t tile = blockIdx.x;
+  const uint32_t G = a.xcd_group, span = 8u * G;
+  if (G > 1 && tile < gridDim.x / span * span) {
+    const uint32_t k = tile % span;
+    tile = tile - k + (k % 8u) * G + k / 8u;
+  }
+  const uint32_t c = tile * blockDim.x + threadIdx.x;
   if (c >= a.ncell) return;
   sweep_cell<L, S, kGeneral>(a, c);
 }
@@ -996,6 +1006,7 @@ __host__ __device__ inline SweepArgs<S> to_args_dev(const SweepHost& h) {
   a.level = h.level;
   a.lstride = h.lstride;
   a.ntiles = 0;
+  a.xcd_group = 1;
   a.rec = (R*)h.rec;
   a.recf = (R*)h.recf;
   a.sp = (const R*)h.sp;
@@ -1029,6 +1040,7 @@ static hipError_t launch_sweep_t(const SweepHost& h, int block, hipStream_t st) 
   SweepArgs<S> a = to_args<S>(h);
   const uint32_t blocks = (a.ncell + block - 1) / block;
   a.ntiles = blocks;
+  a.xcd_group = block < 256 ? 256u / (uint32_t)block : 1u;
   if (h.general)
     hipLaunchKernelGGL((k_sweep<L, S, true>), dim3(blocks), dim3(block), 0, st, a);
   else

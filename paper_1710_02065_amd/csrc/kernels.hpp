@@ -165,6 +165,9 @@ struct SweepArgs {
   int32_t level;
   uint32_t lstride;      // inlet-noise counter blocks per time index
   uint32_t ntiles;
+  // workgroups per XCD run: runs of xcd_group consecutive tiles go to one
+  // XCD (1: plain round-robin)
+  uint32_t xcd_group;
   // refinement: pre-collision moments of the coarse nodes on the patch
   // boundary planes are recorded into rec (10 contiguous components per
   // node of the record box [rec_off, rec_off + rec_dim)); rec == nullptr

@@ -699,12 +699,17 @@ __global__ void __launch_bounds__(1024)
             int32_t s_off) {
   const int32_t s = hdr->step + s_off;
   const uint32_t njobs = hdr->njobs, total = hdr->total_tiles;
+  uint32_t lo = 0;  // job of the previous tile: this workgroup's tiles increase
   for (uint32_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    // last job whose first tile is <= tile
-    uint32_t lo = 0, hi = njobs;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid;
+    // last job whose first tile is <= tile: usually the previous tile's job
+    // (one table read), else a binary search over the jobs after it
+    if (lo + 1 < njobs && jobs[lo + 1].tile_begin <= tile) {
+      uint32_t hi = njobs;
+      ++lo;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid;
+      }
     }
     const BatchJob& J = jobs[lo];
     if ((int64_t)s >= J.steps) continue;

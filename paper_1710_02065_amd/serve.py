@@ -69,12 +69,18 @@ class Server:
     """Admission + continuous batching loop.
 
     budget_bytes: HBM budget for resident jobs; quantum: steps per batched
-    call (a job near its end takes only its remaining steps)."""
+    call (a job near its end takes only its remaining steps); lookahead:
+    batched calls enqueued beyond the one the host waits for.  With
+    lookahead 1 the next quantum is on the device while the host retires
+    the jobs of the previous one and admits new ones, so the device does
+    not idle between quanta; a job's memory returns to the budget once its
+    last quantum has completed."""
 
-    def __init__(self, backend, budget_bytes, quantum=256):
+    def __init__(self, backend, budget_bytes, quantum=256, lookahead=1):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.quantum = int(quantum)
+        self.lookahead = int(lookahead)
 
     def run(self, jobs):
         be = self.backend
@@ -85,10 +91,11 @@ class Server:
                 raise ValueError("job %s needs %d bytes, more than the budget %d"
                                  % (r.job["id"], r.need, self.budget))
         queue, active, done = [], [], []
+        inflight = []  # (completion mark, jobs whose last quantum it closes)
         used = 0
         st = Stats()
         t0 = be.now()
-        while pending or queue or active:
+        while pending or queue or active or inflight:
             now = be.now() - t0
             while pending and pending[0].job["arrival"] <= now:
                 queue.append(pending.pop(0))
@@ -101,7 +108,8 @@ class Server:
             for r in list(queue):
                 if used + r.need > self.budget:
                     if wait is None:
-                        wait = self._steps_until_fits(active, used, r.need)
+                        retiring = [x for _, fin in inflight for x in fin]
+                        wait = self._steps_until_fits(active + retiring, used, r.need)
                     continue
                 if wait is not None and r.job["steps"] > wait:
                     continue
@@ -111,26 +119,38 @@ class Server:
                 queue.remove(r)
                 active.append(r)
             st.peak_bytes = max(st.peak_bytes, used)
-            if not active:
-                if pending:
+            if active:
+                steps = [min(self.quantum, r.remaining) for r in active]
+                be.step([r.handle for r in active], steps)
+                st.quanta += 1
+                for r, n in zip(active, steps):
+                    r.done_steps += n
+                fin = [r for r in active if r.remaining == 0]
+                for r in fin:
+                    # results read out behind this quantum, collected later
+                    r.result = be.retire(r.handle)
+                    active.remove(r)
+                inflight.append((be.mark(), fin))
+            # wait for the oldest quantum once `lookahead` more are queued
+            # behind it (or nothing more can be queued)
+            while inflight and (len(inflight) > self.lookahead or not active):
+                mark, fin = inflight.pop(0)
+                be.wait(mark)
+                for r in fin:
+                    r.result = be.collect(r.handle, r.result)
+                    r.finished = be.now() - t0
+                    used -= r.need
+                    done.append(r)
+                    st.latencies.append(r.finished - r.job["arrival"])
+                    st.queue_delays.append(r.admitted - r.job["arrival"])
+                    st.cell_updates += be.cells(r.job) * r.job["steps"]
+                if active:
+                    break
+            if not active and not inflight:
+                be.idle()
+                if pending and not queue:
                     be.wait_until(t0 + pending[0].job["arrival"])
-                continue
-            steps = [min(self.quantum, r.remaining) for r in active]
-            be.step([r.handle for r in active], steps)
-            be.sync()
-            st.quanta += 1
-            for r, n in zip(active, steps):
-                r.done_steps += n
-            now = be.now() - t0
-            for r in [r for r in active if r.remaining == 0]:
-                r.result = be.finish(r.handle)
-                r.finished = be.now() - t0
-                used -= r.need
-                active.remove(r)
-                done.append(r)
-                st.latencies.append(r.finished - r.job["arrival"])
-                st.queue_delays.append(r.admitted - r.job["arrival"])
-                st.cell_updates += be.cells(r.job) * r.job["steps"]
+        be.idle()
         if done:
             st.makespan = max(r.finished for r in done) - min(r.job["arrival"] for r in done)
         self.records = done
@@ -183,12 +203,24 @@ class FakeBackend:
         self.clock += self.overhead + work / (self.mlups * 1e6)
         self.calls.append([(h["id"], n) for h, n in zip(handles, steps)])
 
-    def sync(self):
+    def retire(self, h):
+        return None
+
+    def mark(self):
+        return self.clock
+
+    def wait(self, mark):
+        pass
+
+    def collect(self, h, pending):
+        del self.live[h["id"]]
+        return h["id"]
+
+    def idle(self):
         pass
 
     def finish(self, h):
-        del self.live[h["id"]]
-        return h["id"]
+        return self.collect(h, self.retire(h))
 
 
 class GpuBackend:
@@ -202,6 +234,9 @@ class GpuBackend:
         self.dev = torch.device("cuda", device)
         self.stream = torch.cuda.current_stream(self.dev).cuda_stream
         self.keep = keep_populations
+        # retired contexts: lbm_destroy waits for the shared stream, so they
+        # are destroyed when the device has nothing queued
+        self.retired = []
 
     def now(self):
         return time.perf_counter()
@@ -272,29 +307,63 @@ class GpuBackend:
     def step(self, handles, steps):
         self.lbm.lbm_step_batch([h["ctx"] for h in handles], steps)
 
-    def sync(self):
-        self.torch.cuda.synchronize(self.dev)
-
-    def finish(self, h):
+    def retire(self, h):
+        """Enqueue the read-out of a job whose last quantum was just
+        enqueued: its density (and, when kept, populations and initial
+        fields) copied into pinned host memory behind that quantum."""
         lbm, t = self.lbm, self.torch
-        job = h["job"]
-        n = self.cells(job)
+        n = self.cells(h["job"])
+
+        def host(x):
+            y = t.empty(x.shape, dtype=x.dtype, pin_memory=True)
+            y.copy_(x, non_blocking=True)
+            return y
+
         rho = t.empty(n, dtype=t.float64, device=self.dev)
         lbm.lbm_moments(h["ctx"], 0, rho, None)
-        out = dict(id=job["id"], rho_mean=None, pops=None)
+        out = dict(rho=host(rho))
         if self.keep:
-            # final populations and density, and the initial fields the job
-            # started from (host copies), for checking a job's result
+            # final populations and the initial fields the job started
+            # from, for checking a job's result
             pops = t.empty(9, n, dtype=t.float64, device=self.dev)
             lbm.lbm_get_populations(h["ctx"], 0, pops)
-            out["pops"] = pops.cpu()
-            out["rho"] = rho.cpu()
+            out["pops"] = host(pops)
             r0, u0, m0 = h["keep"]
-            out["init"] = (r0.cpu().numpy(), u0.cpu().numpy(),
-                           None if m0 is None else m0.cpu().numpy())
-        out["rho_mean"] = float(rho.mean().item())
-        lbm.lbm_sync(h["ctx"])
-        lbm.lbm_destroy(h["ctx"])
+            out["init"] = (host(r0), host(u0), None if m0 is None else host(m0))
+        return out
+
+    def mark(self):
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.dev))
+        return ev
+
+    def wait(self, ev):
+        ev.synchronize()
+
+    def collect(self, h, pending):
+        """Result of a retired job once its read-out has completed; its
+        memory goes back to torch's allocator (stream-ordered reuse) and its
+        context is destroyed at the next idle point."""
+        job = h["job"]
+        out = dict(id=job["id"], rho=pending["rho"], rho_mean=float(pending["rho"].mean()),
+                   pops=pending.get("pops"))
+        if "init" in pending:
+            out["init"] = tuple(None if x is None else x.numpy() for x in pending["init"])
+        self.retired.append(h["ctx"])
         h["ctx"] = None
         del h["mem"], h["keep"]
+        return out
+
+    def idle(self):
+        for ctx in self.retired:
+            self.lbm.lbm_destroy(ctx)
+        self.retired.clear()
+
+    def finish(self, h):
+        """Read out, wait and destroy one job (outside the serving loop)."""
+        pending = self.retire(h)
+        ev = self.mark()
+        self.wait(ev)
+        out = self.collect(h, pending)
+        self.idle()
         return out

@@ -416,11 +416,16 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs<S>& a, uint32_t c) {
 // formats (the HBM stream needs them; without the hint the general path's
 // scalar registers alone would limit it to 7), except the D3Q27 general
 // path, whose 27 pulled values need more than the 64 registers 8 waves
-// leave (7 waves, no spills); no constraint for FP64.
+// leave (7 waves, no spills), and the D3Q27 comparator collisions on either
+// path, which keep the 27 pulled values alive through the rebuild (7 waves:
+// with 64 registers the LBM-BGK sweep spilled 3.5 KB per lane); no
+// constraint for FP64.
 template <class L, class S, bool kGeneral>
 struct SweepWaves {
   static constexpr int value =
-      sizeof(typename S::T) == 8 ? 1 : (L::Q == 27 && kGeneral ? 7 : 8);
+      sizeof(typename S::T) == 8
+          ? 1
+          : (L::Q == 27 && (kGeneral || L::kColl != kCollRR) ? 7 : 8);
 };
 
 template <class L, class S, bool kGeneral>
@@ -690,11 +695,21 @@ __device__ __forceinline__ void batch_cell(const BatchJob& J, int32_t s, uint32_
   sweep_cell<L, S, kGeneral>(a, c);
 }
 
+// Wavefronts per SIMD of the batched sweep: those of the solo sweep, one
+// fewer on the 3D general path, where the job lookup's registers on top of
+// the sweep's made 8 (D3Q19) and 7 (D3Q27) waves spill.
+template <class L, class S, bool kGeneral>
+struct BatchWaves {
+  static constexpr int value =
+      L::D == 3 && kGeneral && sizeof(typename S::T) < 8 ? SweepWaves<L, S, kGeneral>::value - 1
+                                                         : SweepWaves<L, S, kGeneral>::value;
+};
+
 // One kernel per (lattice, storage, path): the contexts of a batch are
 // grouped so, which keeps each kernel as lean as the solo sweep.
 template <class L, class S, bool kGeneral>
 __global__ void __launch_bounds__(1024)
-    __attribute__((amdgpu_waves_per_eu(SweepWaves<L, S, kGeneral>::value)))
+    __attribute__((amdgpu_waves_per_eu(BatchWaves<L, S, kGeneral>::value)))
     k_batch(const BatchJob* __restrict__ jobs, const BatchHeader* __restrict__ hdr,
             int32_t s_off) {
   const int32_t s = hdr->step + s_off;

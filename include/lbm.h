@@ -356,7 +356,7 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n);
  * the same contexts, the same kernels and bitwise the same results as
  * lbm_step_batch, with no hipMalloc, hipFree, host staging allocation or
  * graph instantiation.  The job tables live in a fixed device array of
- * static storage (about 110 KB: LBM_NOALLOC_MAX_JOBS batch headers and
+ * static storage (about 130 KB: LBM_NOALLOC_MAX_JOBS batch headers and
  * jobs) that each device the library runs on holds until the process ends;
  * they are uploaded through kernel arguments and every step is its own
  * batch launch.  The caller still provides the contexts (whose memory

@@ -28,6 +28,25 @@ def test_budget_never_exceeded_and_all_jobs_finish():
     assert total == {j["id"]: j["steps"] for j in js}
 
 
+@pytest.mark.parametrize("lookahead", [0, 1, 2])
+def test_lookahead_keeps_budget_and_steps(lookahead):
+    """With quanta queued ahead of the one the host waits for, a job's memory
+    returns to the budget only once its last quantum has completed, every
+    job still receives exactly its steps, and the budget holds."""
+    js = jobs(n=30, rate=200.0)
+    be = serve.FakeBackend(mlups=2000.0)
+    budget = 3 * max(be.required_bytes(j) for j in js)
+    st = serve.Server(be, budget, quantum=64, lookahead=lookahead).run(js)
+    assert len(st.latencies) == len(js)
+    assert be.max_live_bytes <= budget and st.peak_bytes <= budget
+    total = {}
+    for call in be.calls:
+        for jid, n in call:
+            total[jid] = total.get(jid, 0) + n
+    assert total == {j["id"]: j["steps"] for j in js}
+    assert not be.live
+
+
 def test_queueing_grows_with_load():
     out = []
     for rate in (5.0, 500.0):

@@ -41,7 +41,9 @@ struct MState {
 };
 
 // Workgroup tile: TX x TY interior cells of a plane, HX x HY with the
-// halo; one thread per halo-plane slot (NT >= HX HY, whole wavefronts).
+// halo.  3D: TY wavefronts of interior cells (one lane per cell) and three
+// halo wavefronts (the two halo rows, then both halo columns with their
+// corners); 2D: one thread per halo-row slot (NT >= HX, whole wavefronts).
 template <class L, class R>
 struct MTile {
   static constexpr int TX = L::D == 3 ? 64 : 254;
@@ -49,7 +51,8 @@ struct MTile {
   static constexpr int HX = TX + 2;
   static constexpr int HY = L::D == 3 ? TY + 2 : 1;
   static constexpr int SLOTS = HX * HY;
-  static constexpr int NT = (SLOTS + 63) / 64 * 64;
+  static constexpr int NT = L::D == 3 ? (TY + 3) * 64 : (SLOTS + 63) / 64 * 64;
+  static_assert(L::D == 2 || (TX == 64 && 2 * HY <= 64), "3D halo wavefronts");
   // LDS planes: with two, consecutive iterations alternate and one barrier
   // per plane suffices (measured slower: the doubled LDS halves the
   // workgroups a CU holds)
@@ -64,6 +67,28 @@ constexpr int march_of(int i) {
 template <class L, int HX>
 constexpr int plane_shift(int i) {
   return L::dir(i).x + (L::D == 3 ? L::dir(i).y * HX : 0);
+}
+
+// What a thread rebuilds.  kInterior: its own output cell, every
+// population (those with no in-plane velocity stay in registers);
+// kRowLo / kRowHi: a halo-row cell below / above the tile, only the
+// populations with xi_y = +1 / -1 (the only ones an interior cell pulls
+// from there); kCols: a halo-column cell, only those with xi_x != 0;
+// kAny: one halo-row slot of a 2D row tile, every population.
+enum MRole { kAny = -1, kInterior = 0, kRowLo = 1, kRowHi = 2, kCols = 3 };
+
+template <class L, int ROLE>
+constexpr bool role_needs(int i) {
+  return ROLE == kRowLo   ? L::dir(i).y == 1
+         : ROLE == kRowHi ? L::dir(i).y == -1
+         : ROLE == kCols  ? L::dir(i).x != 0
+                          : true;
+}
+
+// populations of its own cell that an interior thread pulls from registers
+template <class L, int HX, int ROLE>
+constexpr bool in_regs(int i) {
+  return ROLE == kInterior && plane_shift<L, HX>(i) == 0;
 }
 
 template <class R>
@@ -124,53 +149,27 @@ __device__ __forceinline__ R collide_state(const R h[L::Q], R omega1, R rho0,
   return rho;
 }
 
-// ------------------------------------------------------------------------
-// The sweep.  Iteration m (output plane m) writes, for every halo-plane
-// slot of the tile, the populations that stream into plane m: those with
-// a +1 marching component from plane m - 1, 0 from plane m, -1 from plane
-// m + 1 (rebuilt from moments loaded one iteration ahead); the thread
-// keeps the parts it will write in the next two iterations in registers.
-// After a barrier every interior cell pulls its q populations from the
-// slots at x - xi, collides and stores its moments; a second barrier
-// protects the LDS plane before it is rewritten.  The loads are issued
-// for every thread and iteration (threads beyond the halo plane load a
-// valid cell and write nothing), so they stay in flight across the
-// barriers instead of being waited for at a branch.
-// ------------------------------------------------------------------------
-template <class L, class R>
-__global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R> a) {
+// One thread's march through planes m0 ... m1 - 1.  Iteration m (output
+// plane m) writes, for the thread's slot, the populations that stream into
+// plane m: those with a +1 marching component from plane m - 1, 0 from
+// plane m, -1 from plane m + 1 (rebuilt from moments loaded one iteration
+// ahead); the thread keeps the parts it will write in the next two
+// iterations in registers.  After a barrier every interior cell pulls its
+// q populations from the slots at x - xi, collides and stores its moments;
+// a second barrier protects the LDS plane before it is rewritten.  Every
+// thread of a workgroup runs the same number of iterations and barriers.
+// The loads are issued for every thread and iteration (threads without a
+// slot load a valid cell and write nothing), so they stay in flight across
+// the barriers instead of being waited for at a branch.
+template <class L, class R, int ROLE>
+__device__ __forceinline__ void march(const MSweepArgs<R>& a, R* lds, uint32_t scell,
+                                      uint32_t slds, bool sown, uint32_t ocell, uint32_t olds,
+                                      bool oown, uint32_t m0, uint32_t m1) {
   using G = MTile<L, R>;
   constexpr int Q = L::Q, NM = MState<L>::NM;
-  __shared__ R lds_all[G::NB * Q * G::SLOTS];
-
-  uint32_t b = blockIdx.x;
-  if (a.xcd_order) b = (b % 8u) * (a.nblocks / 8u) + b / 8u;
-  const uint32_t bx = b % a.tiles_x;
-  const uint32_t r = b / a.tiles_x;
-  const uint32_t by = r % a.tiles_y;
-  const uint32_t ch = r / a.tiles_y;
-  const uint32_t x0 = bx * G::TX, y0 = by * G::TY;
-  const uint32_t wx = min((uint32_t)G::TX, a.px - x0);
-  const uint32_t wy = L::D == 3 ? min((uint32_t)G::TY, a.py - y0) : 1u;
-  const uint32_t m0 = ch * a.zc, m1 = min(a.pm, m0 + a.zc);
-  const uint32_t hx = wx + 2, hy = L::D == 3 ? wy + 2 : 1u;
+  constexpr bool kCollide = ROLE == kAny || ROLE == kInterior;
   const uint32_t plane = a.px * a.py;
   const uint64_t P = a.pstride;
-  const uint32_t tid = threadIdx.x;
-
-  // the slot this thread rebuilds: plane cell and LDS index
-  const bool sown = tid < hx * hy;
-  const uint32_t sx = sown ? tid % hx : 0u, sy = sown ? tid / hx : 0u;
-  const uint32_t gx = (x0 + sx + a.px - 1) % a.px;
-  const uint32_t gy = L::D == 3 ? (y0 + sy + a.py - 1) % a.py : 0u;
-  const uint32_t scell = gy * a.px + gx;
-  const uint32_t slds = sy * G::HX + sx;
-  // output cell of this thread
-  const uint32_t ox = tid % G::TX, oy = tid / G::TX;
-  const bool oown = tid < (uint32_t)(G::TX * G::TY) && ox < wx && oy < wy;
-  const uint32_t ocell = (y0 + oy) * a.px + x0 + ox;
-  const uint32_t olds = (L::D == 3 ? (oy + 1) * G::HX : 0u) + ox + 1;
-
   auto wrap_m = [&](uint32_t m, int d) -> uint32_t {
     return (m + a.pm + (uint32_t)d) % a.pm;
   };
@@ -179,8 +178,11 @@ __global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R
   // mid = 0 part of plane m; nxt = moments of plane m + 1.  Two warm-up
   // iterations fill them through the same code as the others (so every
   // plane is rebuilt by the same instructions whatever the chunk length).
+  // Populations the role does not need are never used and drop out.
   R up1[Q], up2[Q], mid[Q], nxt[NM];
   load_state<L, R>(a.src, P, wrap_m(m0, -1) * plane + scell, nxt);
+  // not unrolled or peeled: a peeled warm-up copy may round differently
+#pragma clang loop unroll(disable)
   for (int it = -2; it < (int)(m1 - m0); ++it) {
     R v[Q];
     {
@@ -204,29 +206,107 @@ __global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R
     }
     if (it < 0) continue;
     const uint32_t m = m0 + (uint32_t)it;
-    R* lds = lds_all + (G::NB == 2 ? (uint32_t)(it & 1) * (Q * G::SLOTS) : 0u);
+    R* buf = lds + (G::NB == 2 ? (uint32_t)(it & 1) * (Q * G::SLOTS) : 0u);
     if (sown) {
       static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        lds[i * G::SLOTS + slds] = v[i];
+        if constexpr (role_needs<L, ROLE>(i) && !in_regs<L, G::HX, ROLE>(i)) buf[i * G::SLOTS + slds] = v[i];
       });
     }
     __syncthreads();
-    if (oown) {
-      R h[Q], mo[NM];
-      static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        h[i] = lds[i * G::SLOTS + (int)olds - plane_shift<L, G::HX>(i)];
-      });
-      const R rho = collide_state<L, R>(h, a.omega1, a.rho0, mo);
-      // stability watchdog: a rare, benign racy store of 1
-      if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
-      const uint32_t c = m * plane + ocell;
+    if constexpr (kCollide) {
+      if (oown) {
+        R h[Q], mo[NM];
+        static_for<0, Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (in_regs<L, G::HX, ROLE>(i))
+            h[i] = v[i];
+          else
+            h[i] = buf[i * G::SLOTS + (int)olds - plane_shift<L, G::HX>(i)];
+        });
+        const R rho = collide_state<L, R>(h, a.omega1, a.rho0, mo);
+        // stability watchdog: a rare, benign racy store of 1
+        if (!(rho > (R)0) || !(rho < (R)1e30)) a.status[0] = 1;
+        const uint32_t c = m * plane + ocell;
 #pragma unroll
-      for (int k = 0; k < NM; ++k)
-        store_pop_nt(a.dst + (uint64_t)k * P, (uint32_t)(P * sizeof(R)), c, mo[k]);
+        for (int k = 0; k < NM; ++k)
+          store_pop_nt(a.dst + (uint64_t)k * P, (uint32_t)(P * sizeof(R)), c, mo[k]);
+      }
     }
     if constexpr (G::NB == 1) __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// The sweep: one workgroup per tile and chunk of planes.  In 3D the
+// wavefront index (uniform, read into a scalar register) selects the role,
+// so each wavefront runs one specialised march and the halo wavefronts
+// rebuild only the populations the interior pulls from them (5 of 19 on
+// the rows, 10 of 19 on the columns for D3Q19).
+// ------------------------------------------------------------------------
+template <class L, class R>
+__global__ void __launch_bounds__((MTile<L, R>::NT)) k_msweep(const MSweepArgs<R> a) {
+  using G = MTile<L, R>;
+  __shared__ R lds_all[G::NB * L::Q * G::SLOTS];
+
+  uint32_t b = blockIdx.x;
+  if (a.xcd_order) b = (b % 8u) * (a.nblocks / 8u) + b / 8u;
+  const uint32_t bx = b % a.tiles_x;
+  const uint32_t r = b / a.tiles_x;
+  const uint32_t by = r % a.tiles_y;
+  const uint32_t ch = r / a.tiles_y;
+  const uint32_t x0 = bx * G::TX, y0 = by * G::TY;
+  const uint32_t wx = min((uint32_t)G::TX, a.px - x0);
+  const uint32_t wy = L::D == 3 ? min((uint32_t)G::TY, a.py - y0) : 1u;
+  const uint32_t m0 = ch * a.zc, m1 = min(a.pm, m0 + a.zc);
+  const uint32_t tid = threadIdx.x;
+
+  if constexpr (L::D == 3) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / 64u);
+    const uint32_t lane = tid % 64u;
+    const uint32_t hy = wy + 2;
+    if (wave < (uint32_t)G::TY) {
+      // interior: lane = x, wave = y of the output cell, which is also the
+      // slot it rebuilds; lanes outside a ragged tile load a valid cell
+      const bool own = lane < wx && wave < wy;
+      const uint32_t ox = min(lane, wx - 1), oy = min(wave, wy - 1);
+      const uint32_t ocell = (y0 + oy) * a.px + x0 + ox;
+      const uint32_t olds = (oy + 1) * G::HX + ox + 1;
+      march<L, R, kInterior>(a, lds_all, ocell, olds, own, ocell, olds, own, m0, m1);
+    } else if (wave < (uint32_t)G::TY + 2) {
+      // halo row below (y0 - 1) or above (y0 + wy) the tile, x0 ... x0 + wx - 1
+      const bool lo = wave == (uint32_t)G::TY;
+      const uint32_t sx = min(lane, wx - 1) + 1, sy = lo ? 0u : wy + 1;
+      const uint32_t gy = lo ? (y0 + a.py - 1) % a.py : (y0 + wy) % a.py;
+      const uint32_t scell = gy * a.px + x0 + sx - 1;
+      const uint32_t slds = sy * G::HX + sx;
+      if (lo)
+        march<L, R, kRowLo>(a, lds_all, scell, slds, lane < wx, 0u, 0u, false, m0, m1);
+      else
+        march<L, R, kRowHi>(a, lds_all, scell, slds, lane < wx, 0u, 0u, false, m0, m1);
+    } else {
+      // halo columns x0 - 1 (lanes 0 ... hy - 1) and x0 + wx (the next hy
+      // lanes), halo rows included.  The clamp of the idle lanes follows
+      // the select: with it inside the second arm (min(lane - hy, hy - 1))
+      // this compiler (ROCm 7.2 clang) dropped the first arm from the
+      // device code.
+      const bool left = lane < hy;
+      const uint32_t sy = min(left ? lane : lane - hy, hy - 1);
+      const uint32_t sx = left ? 0u : wx + 1;
+      const uint32_t gx = left ? (x0 + a.px - 1) % a.px : (x0 + wx) % a.px;
+      const uint32_t gy = (y0 + sy + a.py - 1) % a.py;
+      march<L, R, kCols>(a, lds_all, gy * a.px + gx, sy * G::HX + sx, lane < 2 * hy, 0u, 0u,
+                         false, m0, m1);
+    }
+  } else {
+    // 2D: thread = slot of the halo row (x0 - 1 ... x0 + wx), the first wx
+    // threads also own the output cells x0 ... x0 + wx - 1
+    const uint32_t hx = wx + 2;
+    const bool sown = tid < hx;
+    const uint32_t sx = sown ? tid : 0u;
+    const uint32_t scell = (x0 + sx + a.px - 1) % a.px;
+    const bool oown = tid < wx;
+    march<L, R, kAny>(a, lds_all, scell, sx, sown, y0 * a.px + x0 + tid, tid + 1, oown, m0, m1);
   }
 }
 

@@ -342,7 +342,11 @@ int lbm_set_interface(lbm_ctx* ctx, int level, const void* in);
 /* Serving: advance ctxs[k] by steps[k] coarse steps, k < n, sharing
  * launches between contexts: the contexts are grouped by lattice, storage,
  * sweep path (fully periodic or not) and workgroup size, and each group
- * advances through one persistent launch per step.  All contexts must be
+ * advances through one persistent launch per step.  The first group runs
+ * on the contexts' stream, the others concurrently on streams the library
+ * owns, ordered after and joined back into the contexts' stream with
+ * events, so work queued on that stream before the call precedes every
+ * group and work queued after it follows them all.  All contexts must be
  * unrefined, without halo faces, on one device and one stream, and
  * initialised.  Each context's
  * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */

@@ -37,9 +37,26 @@ struct BatchRunner {
   hipStream_t capture = nullptr;
   std::map<std::pair<int, int>, GraphEntry> graphs;  // (kernel variant, block)
   std::map<std::pair<int, int>, int> grids;
+  // Lanes: the second and later groups of a batch run on runners of their
+  // own with their own streams, concurrently with the first group (on the
+  // caller's stream): ordered after the caller's stream by `fork`, joined
+  // back into it by each lane's `done`.
+  std::vector<BatchRunner*> lanes;
+  hipEvent_t fork = nullptr;
+  hipEvent_t done = nullptr;
 };
 
 static std::mutex g_batch_mu;
+
+static hipError_t setup_runner(BatchRunner* r) {
+  hipError_t e = hipMalloc(&r->d_hdr, sizeof(BatchHeader));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_hdr, sizeof(BatchHeader), 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->capture, hipStreamNonBlocking);
+  return e;
+}
 static std::map<std::pair<int, hipStream_t>, BatchRunner*> g_runners;
 
 static int runner_for(int device, hipStream_t st, BatchRunner** out) {
@@ -52,16 +69,32 @@ static int runner_for(int device, hipStream_t st, BatchRunner** out) {
   BatchRunner* r = new BatchRunner();
   r->device = device;
   r->stream = st;
-  hipError_t e = hipMalloc(&r->d_hdr, sizeof(BatchHeader));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_hdr, sizeof(BatchHeader), 0);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->staged, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->capture, hipStreamNonBlocking);
+  hipError_t e = setup_runner(r);
   if (e != hipSuccess) {
     delete r;
     return hip_error(e, "batch runner setup");
   }
   g_runners[key] = r;
   *out = r;
+  return LBM_OK;
+}
+
+// Lane k of a runner (created on first use; streams at the default
+// priority).
+static int lane_for(BatchRunner* r, size_t k, BatchRunner** out) {
+  while (r->lanes.size() <= k) {
+    BatchRunner* l = new BatchRunner();
+    l->device = r->device;
+    hipError_t e = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = setup_runner(l);
+    if (e != hipSuccess) {
+      if (l->stream) (void)hipStreamDestroy(l->stream);
+      delete l;
+      return hip_error(e, "batch lane setup");
+    }
+    r->lanes.push_back(l);
+  }
+  *out = r->lanes[k];
   return LBM_OK;
 }
 
@@ -451,11 +484,33 @@ int lbm_step_batch(lbm_ctx* const* ctxs, const int64_t* steps, int n) {
   for (int k = 0; k < n; ++k)
     groups[std::make_pair(batch_variant(ctxs[k]), ctxs[k]->block)].push_back(
         {ctxs[k], steps[k]});
+  if (groups.size() == 1) return run_group(r, groups.begin()->second);
+  // groups after the first run concurrently on lanes (one stream each):
+  // a small group's launches fill the device poorly on their own
+  hipError_t e = hipEventRecord(r->fork, r->stream);
+  if (e != hipSuccess) return hip_error(e, "batch fork");
+  size_t g = 0;
   for (auto& kv : groups) {
-    rc = run_group(r, kv.second);
-    if (rc != LBM_OK) return rc;
+    BatchRunner* x = r;
+    if (g > 0) {
+      rc = lane_for(r, g - 1, &x);
+      if (rc != LBM_OK) break;
+      e = hipStreamWaitEvent(x->stream, r->fork, 0);
+      if (e != hipSuccess) {
+        rc = hip_error(e, "batch lane wait");
+        break;
+      }
+    }
+    rc = run_group(x, kv.second);
+    if (g > 0) {
+      e = hipEventRecord(x->done, x->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, x->done, 0);
+      if (e != hipSuccess && rc == LBM_OK) rc = hip_error(e, "batch lane join");
+    }
+    if (rc != LBM_OK) break;
+    ++g;
   }
-  return LBM_OK;
+  return rc;
 }
 
 int lbm_step_batch_noalloc(lbm_ctx* const* ctxs, const int64_t* steps, int n) {

@@ -268,6 +268,46 @@ def test_step_batch_equals_solo():
             assert s.time == n
 
 
+def test_step_batch_concurrent_groups_equal_solo():
+    """Eight groups in one batched call (FP32 / F16S storage x periodic /
+    general path x workgroup 128 / 256): the first runs on the contexts'
+    stream, the other seven on streams of the library's own, joined back
+    before the populations are read on the contexts' stream without a
+    host synchronisation.  Two calls in a row (the second reuses the
+    streams and the captured graphs), step counts with graph replays,
+    tails and an idle job, a large job beside small ones: every context
+    bitwise equal to stepping it alone."""
+    from paper_1710_02065_amd import lbm
+    periodic = dict(q=9, tau=0.6)
+    general = dict(q=9, tau=0.7, face_bc=(2, 2, 1, 1, 0, 0), sponge_width=(0, 8, 0, 0, 0, 0),
+                   chi_max=0.2)
+    cases, blocks = [], []
+    for storage in ("f32", "f16s"):
+        for kind, base in (("periodic", periodic), ("general", general)):
+            for block in (128, 256):
+                shape = (512, 384, 1) if (storage, kind, block) == ("f32", "general", 128) \
+                    else (48 + 8 * len(cases), 37, 1)
+                cases.append(dict(base, name="%s-%s-%d" % (storage, kind, block), shape=shape,
+                                  storage=storage))
+                blocks.append(block)
+    first = [40, 13, 77, 0, 33, 16, 5, 21]
+    second = [17, 32, 3, 18, 0, 48, 29, 7]
+    fields = [W.random_state(c["shape"], seed=90 + k, d=2) for k, c in enumerate(cases)]
+    solo = []
+    for c, f, b, n1, n2 in zip(cases, fields, blocks, first, second):
+        log("batch lanes solo %s" % c["name"])
+        solo.append(gpu_sim(c, c["storage"], block=b).init(*f).step(n1 + n2)
+                    .populations().cpu().numpy())
+    sims = [gpu_sim(c, c["storage"], block=b).init(*f) for c, f, b in zip(cases, fields, blocks)]
+    log("batch lanes: two batched calls over eight groups")
+    lbm.lbm_step_batch([s.ctx for s in sims], first)
+    lbm.lbm_step_batch([s.ctx for s in sims], second)
+    got = [s.populations() for s in sims]  # queued on the contexts' stream
+    for s, g, ref, c, n1, n2 in zip(sims, got, solo, cases, first, second):
+        np.testing.assert_array_equal(g.cpu().numpy(), ref, err_msg=c["name"])
+        assert s.time == n1 + n2
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_full_size_d3q19_sampled_parity(storage):
     """D3Q19 256^3 periodic, Taylor-Green + acoustic pulse, in the launch

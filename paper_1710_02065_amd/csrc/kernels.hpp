@@ -116,6 +116,12 @@ __device__ __forceinline__ T load_pop(const T* base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
                                      (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
+// The same load with the non-temporal hint (streamed through the caches).
+template <class T>
+__device__ __forceinline__ T load_pop_nt(const T* base, uint32_t idx) {
+  return __builtin_nontemporal_load(reinterpret_cast<const T*>(
+      reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))));
+}
 // Non-temporal store of element idx of a population array through a raw
 // buffer resource (scalar base, 32-bit offset, stores past `bytes` are
 // dropped by the hardware).  The third resource word 0x00020000 is the

@@ -14,10 +14,10 @@
 // y in 2D).  For each plane a workgroup rebuilds the post-collision
 // populations of its tile plus a one-cell halo into LDS (each population
 // from the plane it streams out of), pulls every interior cell's q
-// populations from there, collides, and stores the new moments.  Each
-// cell's plane is rebuilt once per workgroup that needs it; the halo cells
-// are rebuilt by both neighbouring tiles and their moments re-read from
-// L2.
+// populations from there, collides, and stores the new moments.  A halo
+// cell is rebuilt again by the neighbouring tile, only for the populations
+// that tile pulls from it, and its moments are read again (from L2 when
+// the neighbour read them recently).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

@@ -346,7 +346,10 @@ int lbm_set_interface(lbm_ctx* ctx, int level, const void* in);
  * on the contexts' stream, the others concurrently on streams the library
  * owns, ordered after and joined back into the contexts' stream with
  * events, so work queued on that stream before the call precedes every
- * group and work queued after it follows them all.  All contexts must be
+ * group and work queued after it follows them all.  Per device and
+ * contexts' stream the library keeps, until the process ends, a job table,
+ * its captured graphs and, for the groups after the first, one stream with
+ * its own table each.  All contexts must be
  * unrefined, without halo faces, on one device and one stream, and
  * initialised.  Each context's
  * result is bitwise the same as lbm_step(ctxs[k], steps[k]) alone. */
